@@ -1,0 +1,148 @@
+/*
+ * sss.h -- speculative segmented sum CSR SpMV on AMD MI355X (gfx950).
+ *
+ * Computes y = A x for an m x n CSR matrix A (Section 1 states the problem;
+ * Section 2.1 defines the CSR arrays): row_ptr (m+1 int32 offsets, row_ptr[0]
+ * = 0, non-decreasing, row_ptr[m] = nnz), col (nnz int32 column indices in
+ * [0, n)) and val (nnz values).  Rows may be empty; columns need not be sorted
+ * or unique within a row.
+ *
+ * The method is the two-stage speculative segmented sum (Section 3): nnz is cut
+ * into tiles of W*T nonzeros (T = 64, the wavefront width), each wavefront
+ * ("thread-bunch") handles S consecutive tiles, a binary search of row_ptr
+ * gives each tile's first row, a segment descriptor built on chip marks row
+ * heads, a segmented sum produces compact partial sums that are stored to y at
+ * speculated positions, and tiles that contain empty rows are labelled dirty.
+ * The second stage -- which the paper runs on a CPU core -- runs here as a
+ * device fixup kernel: it adds the carries that cross thread-bunches (the
+ * synchronizer) and moves the dirty tiles' partial sums to their rows.
+ *
+ * Memory and ownership
+ *   All matrix and vector pointers passed to execute calls are caller-owned
+ *   DEVICE pointers on the current HIP device; the library never frees or
+ *   retains them past the call.  col and val must be 16-byte aligned (any
+ *   hipMalloc / PyTorch allocation is).  A plan owns its auxiliary device
+ *   buffers (synchronizer, dirty counter, speculator) from create to destroy.
+ *   y is overwritten (not accumulated into).
+ *
+ * Streams
+ *   `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Execute calls only enqueue work: no allocation, no host synchronisation,
+ *   so they can be captured in a HIP graph.  Calls that share a plan must be
+ *   ordered on one stream: a plan's auxiliary buffers serve one call at a time.
+ *
+ * Errors
+ *   Every call returns an sss_status.  SSS_ERR_HIP keeps the HIP error, which
+ *   sss_last_hip_error() describes (thread-local).
+ */
+#ifndef SSS_H
+#define SSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SSS_OK = 0,
+  SSS_ERR_INVALID_VALUE = -1,  /* negative size, null pointer with nonzero size, bad option, misaligned */
+  SSS_ERR_UNSUPPORTED = -2,    /* dtype or parameter combination not built */
+  SSS_ERR_PLAN_MISMATCH = -3,  /* plan used with sizes or dtype it was not made for */
+  SSS_ERR_HIP = -4,            /* a HIP runtime call failed */
+  SSS_ERR_INVALID_CSR = -5     /* sss_validate_csr found a malformed matrix */
+} sss_status;
+
+/* Value type.  SSS_F64: val, x, y are double.  SSS_F32: val, x, y are float.
+ * SSS_BF16: val is bfloat16 (uint16 bit patterns), x and y are float.  The
+ * reduced-precision types multiply in float, sum segments with compensated
+ * (TwoSum) float arithmetic, and keep the carries between tiles and between
+ * thread-bunches, and the fixup sums, in double. */
+typedef enum { SSS_F64 = 0, SSS_F32 = 1, SSS_BF16 = 2 } sss_dtype;
+
+/* How a plan chooses (W, S): FIXED takes opts.W/S/B; GRID times every class of
+ * the parameter grid on the caller's matrix and keeps the fastest; SELECTOR
+ * asks the trained selector network (falling back to the defaults if none is
+ * loaded). */
+typedef enum { SSS_MODE_SELECTOR = 0, SSS_MODE_GRID = 1, SSS_MODE_FIXED = 2 } sss_mode;
+
+typedef struct {
+  int mode;  /* sss_mode */
+  int W;     /* nonzeros per lane: 4, 8 or 16 (0 = default for the dtype) */
+  int S;     /* tiles per wavefront, 1..16 (0 = default) */
+  int B;     /* wavefronts per workgroup, 1..4 (0 = default) */
+  int debug; /* nonzero: stage 1 also records tile start rows, segment
+                descriptors and dirty flags for sss_plan_debug_dump */
+} sss_plan_opts;
+
+typedef struct sss_plan_s *sss_plan;
+
+/* Create a plan for an m x n matrix with nnz nonzeros of value type dt.
+ * Section 3.3 sizes the auxiliary arrays it allocates: the synchronizer has
+ * one entry per thread-bunch, ceil(nnz / (S W T)); the speculator one per
+ * tile, ceil(nnz / (W T)); the dirty counter is one integer.
+ * row_ptr (device, may be NULL in FIXED mode) is read only by the GRID and
+ * SELECTOR modes, on `stream`, which this call then synchronises.
+ * opts may be NULL (FIXED with the defaults).  Returns the plan in *out. */
+int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                             sss_dtype dt, const sss_plan_opts *opts, void *stream,
+                             sss_plan *out);
+
+/* y = A x with a plan (both stages of Section 3.2, enqueued on `stream`).
+ * The sizes are the plan's; val/x/y types follow the plan's dtype.  m = 0 is a
+ * no-op; nnz = 0 zeroes y.  SSS_ERR_INVALID_VALUE for a NULL plan, a NULL
+ * pointer whose array is non-empty, or misaligned col/val.  SSS_ERR_PLAN_MISMATCH
+ * if the plan was created on another device. */
+int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col,
+                         const void *val, const void *x, void *y, void *stream);
+
+/* The one-call form of the method in double precision: y = A x with the
+ * default parameters.  Keeps an internal plan per (device, m, nnz) that it
+ * allocates on first use (so the first call for a new size is not
+ * graph-capturable; later calls are). */
+int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                 const int32_t *col, const double *val, const double *x, double *y,
+                 void *stream);
+
+/* Free a plan's device buffers (synchronises the device first). NULL is OK. */
+int sss_plan_destroy(sss_plan p);
+
+/* The plan's chosen parameters and sizes (host integers, any may be NULL). */
+int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t *n_bunches);
+
+/* Debug: check row_ptr[0] = 0, monotone row_ptr, row_ptr[m] = nnz and every
+ * column in [0, n), on the device.  Synchronises `stream`.  Returns SSS_OK or
+ * SSS_ERR_INVALID_CSR. */
+int sss_validate_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                     const int32_t *col, void *stream);
+
+/* Debug: bytes needed by sss_plan_debug_dump for this plan. */
+int sss_plan_debug_size(sss_plan p, size_t *bytes);
+
+/* Debug: copy the last execute's intermediate state to host memory (waits for
+ * the device).  Layout, all little-endian:
+ *   int64 header[4] = {n_tiles, n_bunches, dirty_count, words_per_tile}
+ *   int32 tile_start[n_tiles]          (debug plans only, else zeros)
+ *   int32 tile_dirty[n_tiles]          (debug plans only, else zeros)
+ *   uint32 heads[n_tiles * words_per_tile]  segment descriptor bits, bit k of
+ *          word w = entry 32w+k of the tile, forced first bit included
+ *   int32 speculator[n_tiles * 4]      {start, stop, tile, 0}; the first
+ *          dirty_count entries are valid, in the order of the atomic increments
+ *   int32 sync_idx[n_bunches]
+ *   double sync_val[n_bunches]
+ * Section 3.2 and the appendix algorithm define these arrays. */
+int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes);
+
+/* Human-readable status; sss_last_hip_error the last HIP failure (thread). */
+const char *sss_status_string(int status);
+const char *sss_last_hip_error(void);
+
+/* Library version string. */
+const char *sss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSS_H */

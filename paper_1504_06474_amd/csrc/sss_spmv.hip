@@ -1,0 +1,840 @@
+// Speculative segmented sum CSR SpMV for gfx950 (MI355X), y = A x.
+//
+// Stage 1 (Section 3.2, the appendix algorithm's first-stage function): one
+// 64-lane wavefront per thread-bunch of S tiles, each tile W*64 nonzeros
+// (Section 3.1).  Per bunch:
+//   * the bunch's first row r0 = rightmost row with row_ptr[r] <= b0, by a
+//     wave-parallel 64-ary search (each round narrows the range 64x with one
+//     load per lane and a ballot);
+//   * one pass over the bunch's rows in 64-row chunks builds the segment
+//     descriptor of all S tiles as a bit mask in LDS (head at row_ptr[r] - b0
+//     for each non-empty row), finds every tile's start row (the rightmost
+//     match of each tile boundary, counted by ballots) and detects the dirty
+//     tiles (an empty row among rows start..stop-1 of the tile);
+//   * per tile: coalesced vector loads of col/val (lane j owns entries
+//     [jW, jW+W)), gathers of x, products in registers, a per-lane sequential
+//     segmented reduction, a 64-lane segmented scan of the lanes' open
+//     segments (shuffles), an exclusive scan of head counts giving each partial
+//     sum its compact rank q, and the store of partial q to y[start + q].
+//     The bunch's first segment goes to the synchronizer instead; a tile that
+//     ends inside row `stop` hands its last partial to the next tile through
+//     the transmitter.  Dirty tiles are appended to the speculator with one
+//     atomic increment of the dirty counter.
+// Stage 2 (Section 3.2, checking prediction; the paper runs it on a CPU core)
+// is one device kernel with three independent parts: the synchronizer carries
+// (one thread per run of bunches sharing a first row), the re-arrangement of
+// each dirty tile's partial sums to its non-empty rows (one wavefront per
+// speculator entry), and zeroing the leading empty rows no tile covers.
+//
+// Difference from the paper's listing, on purpose: a dirty tile that ends
+// inside row `stop` also passes its last partial on through the transmitter
+// and writes it at y[stop] (its true row), where the listing clears the
+// transmitter and leaves that partial to the re-arrangement.  The result is
+// the same sum; the gain is that the re-arrangement then only touches rows
+// strictly inside dirty tiles, so all three parts of stage 2 are disjoint and
+// run concurrently in one launch, with no ordering between them.
+//
+// Precision: F64 sums in double.  F32/BF16 multiply in float and sum segments
+// with TwoSum-compensated float pairs; each partial is formed in double, the
+// transmitter, the synchronizer and the stage-2 carry sums are double.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "sss.h"
+
+namespace {
+
+constexpr int kWave = 64;
+
+thread_local hipError_t g_last_hip = hipSuccess;
+
+#define SSS_HIP(call)                         \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) {                   \
+      g_last_hip = e_;                        \
+      return SSS_ERR_HIP;                     \
+    }                                         \
+  } while (0)
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------- value types
+
+template <int DT> struct VT;
+template <> struct VT<SSS_F64> { using val_t = double;   using x_t = double; using y_t = double; using prod_t = double; };
+template <> struct VT<SSS_F32> { using val_t = float;    using x_t = float;  using y_t = float;  using prod_t = float; };
+template <> struct VT<SSS_BF16>{ using val_t = uint16_t; using x_t = float;  using y_t = float;  using prod_t = float; };
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) {
+  return __uint_as_float(bits16 << 16);
+}
+
+// Accumulators.  F64: one double.  F32/BF16: an unevaluated float pair
+// (hi, lo) kept by TwoSum (Knuth), i.e. compensated summation.
+struct AccD {
+  double s;
+  __device__ __forceinline__ void zero() { s = 0.0; }
+  __device__ __forceinline__ void add(double v) { s += v; }
+  // this := earlier (+) this
+  __device__ __forceinline__ void prepend(const AccD &earlier) { s = earlier.s + s; }
+  __device__ __forceinline__ double value() const { return s; }
+  __device__ __forceinline__ AccD shfl_up(unsigned d) const { AccD r; r.s = __shfl_up(s, d, kWave); return r; }
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  const float z = s - a;
+  e = (a - (s - z)) + (b - z);
+}
+
+struct AccC {
+  float hi, lo;
+  __device__ __forceinline__ void zero() { hi = 0.f; lo = 0.f; }
+  __device__ __forceinline__ void add(float v) {
+    float s, e;
+    two_sum(hi, v, s, e);
+    hi = s;
+    lo += e;
+  }
+  // this := earlier (+) this, as a float pair
+  __device__ __forceinline__ void prepend(const AccC &earlier) {
+    float s, e;
+    two_sum(earlier.hi, hi, s, e);
+    e += earlier.lo + lo;
+    hi = s + e;  // renormalise (fast two-sum; |s| >= |e| up to rounding)
+    lo = e - (hi - s);
+  }
+  __device__ __forceinline__ double value() const { return (double)hi + (double)lo; }
+  __device__ __forceinline__ AccC shfl_up(unsigned d) const {
+    AccC r;
+    r.hi = __shfl_up(hi, d, kWave);
+    r.lo = __shfl_up(lo, d, kWave);
+    return r;
+  }
+};
+
+template <int DT> struct AccSel { using type = AccC; };
+template <> struct AccSel<SSS_F64> { using type = AccD; };
+template <int DT> using Acc = typename AccSel<DT>::type;
+
+// ---------------------------------------------------------------- loads
+
+// Lane-contiguous loads of W entries starting at k0 (k0 a multiple of W, the
+// arrays 16-byte aligned).
+template <int W>
+__device__ __forceinline__ void load_cols(const int32_t *__restrict__ col, int k0, int (&c)[W]) {
+  static_assert(W % 4 == 0, "W must be a multiple of 4");
+  const v4i *p = reinterpret_cast<const v4i *>(col + k0);
+#pragma unroll
+  for (int i = 0; i < W / 4; ++i) {
+    v4i v = __builtin_nontemporal_load(p + i);
+    c[4 * i + 0] = v.x; c[4 * i + 1] = v.y; c[4 * i + 2] = v.z; c[4 * i + 3] = v.w;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void load_vals(const double *__restrict__ val, int k0, double (&a)[W]) {
+  const v2d *p = reinterpret_cast<const v2d *>(val + k0);
+#pragma unroll
+  for (int i = 0; i < W / 2; ++i) {
+    v2d v = __builtin_nontemporal_load(p + i);
+    a[2 * i] = v.x; a[2 * i + 1] = v.y;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void load_vals(const float *__restrict__ val, int k0, float (&a)[W]) {
+  const v4f *p = reinterpret_cast<const v4f *>(val + k0);
+#pragma unroll
+  for (int i = 0; i < W / 4; ++i) {
+    v4f v = __builtin_nontemporal_load(p + i);
+    a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void load_vals(const uint16_t *__restrict__ val, int k0, float (&a)[W]) {
+  if constexpr (W % 8 == 0) {
+    const v4u *p = reinterpret_cast<const v4u *>(val + k0);
+#pragma unroll
+    for (int i = 0; i < W / 8; ++i) {
+      v4u v = __builtin_nontemporal_load(p + i);
+      unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a[8 * i + 2 * j] = bf16_to_f32(w[j] & 0xffffu);
+        a[8 * i + 2 * j + 1] = bf16_to_f32(w[j] >> 16);
+      }
+    }
+  } else {
+    const v2u *p = reinterpret_cast<const v2u *>(val + k0);
+#pragma unroll
+    for (int i = 0; i < W / 4; ++i) {
+      v2u v = __builtin_nontemporal_load(p + i);
+      a[4 * i] = bf16_to_f32(v.x & 0xffffu);
+      a[4 * i + 1] = bf16_to_f32(v.x >> 16);
+      a[4 * i + 2] = bf16_to_f32(v.y & 0xffffu);
+      a[4 * i + 3] = bf16_to_f32(v.y >> 16);
+    }
+  }
+}
+
+__device__ __forceinline__ double scalar_val(const double *v, int k) { return v[k]; }
+__device__ __forceinline__ float scalar_val(const float *v, int k) { return v[k]; }
+__device__ __forceinline__ float scalar_val(const uint16_t *v, int k) { return bf16_to_f32(v[k]); }
+
+// ---------------------------------------------------------------- search
+
+// Largest r in [0, m] with rp[r] <= b (rp non-decreasing, rp[0] = 0 <= b).
+// Wave-parallel 64-ary search: each round the 64 lanes probe 64 evenly spaced
+// points of (lo, hi]; the predicate rp[p] <= b holds for a prefix of lanes, so
+// its ballot's popcount picks the sub-interval.
+__device__ __forceinline__ int wave_rightmost(const int32_t *__restrict__ rp, int m, int b, int lane) {
+  int lo = 0, hi = m;
+  while (hi - lo >= kWave) {
+    const int64_t span = hi - lo;
+    const int p = lo + (int)(((int64_t)(lane + 1) * span) / kWave);
+    const uint64_t bal = __ballot(rp[p] <= b);
+    const int c = __popcll(bal);
+    const int newlo = c > 0 ? lo + (int)(((int64_t)c * span) / kWave) : lo;
+    const int newhi = c < kWave ? lo + (int)(((int64_t)(c + 1) * span) / kWave) - 1 : hi;
+    lo = newlo;
+    hi = newhi;
+  }
+  const int p = lo + lane;
+  const bool pred = (p <= hi) && (rp[min(p, hi)] <= b);
+  return lo + __popcll(__ballot(pred)) - 1;
+}
+
+// ---------------------------------------------------------------- stage 1
+
+struct Stage1Args {
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const void *val;
+  const void *x;
+  void *y;
+  int32_t m;
+  int32_t nnz;
+  int32_t S;
+  int64_t n_bunches;
+  int64_t n_tiles;
+  int *counters;        // [0] dirty counter, [1] fixup block counter, [2] last dirty count
+  int4 *speculator;     // <start, stop, tile, 0>
+  int32_t *sync_idx;
+  double *sync_val;
+  int32_t *dbg_start;   // debug plans only
+  int32_t *dbg_dirty;
+  uint32_t *dbg_heads;
+};
+
+template <int DT, int W, bool DEBUG>
+__global__ __launch_bounds__(256) void sss_stage1(Stage1Args a) {
+  using val_t = typename VT<DT>::val_t;
+  using x_t = typename VT<DT>::x_t;
+  using y_t = typename VT<DT>::y_t;
+  using prod_t = typename VT<DT>::prod_t;
+  constexpr int WT = W * kWave;
+  constexpr int WPT = WT / 32;  // descriptor words per tile
+  constexpr uint32_t LOW = (W >= 32) ? 0xffffffffu : ((1u << W) - 1u);
+
+  extern __shared__ uint32_t lds_words[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
+  if (tb >= a.n_bunches) return;
+
+  const int32_t *__restrict__ rp = a.row_ptr;
+  const int32_t *__restrict__ col = a.col;
+  const val_t *__restrict__ val = static_cast<const val_t *>(a.val);
+  const x_t *__restrict__ x = static_cast<const x_t *>(a.x);
+  y_t *__restrict__ y = static_cast<y_t *>(a.y);
+  const int m = a.m, nnz = a.nnz, S = a.S;
+  uint32_t *mask = lds_words + wid * (S * WPT);
+
+  const int64_t SWT = (int64_t)S * WT;
+  const int b0 = (int)(tb * SWT);  // < nnz
+  const int bS = (int)min<int64_t>(tb * SWT + SWT, nnz);
+
+  // ---- tile boundary search (rightmost match) for the bunch's first row
+  const int r0 = wave_rightmost(rp, m, b0, lane);
+
+  // ---- descriptor, tile start rows, dirty tiles: one pass over the rows
+  for (int i = lane; i < S * WPT; i += kWave) mask[i] = 0u;
+  __builtin_amdgcn_wave_barrier();
+
+  const int my_b = (int)min<int64_t>(tb * SWT + (int64_t)min(lane, S) * WT, nnz);
+  int my_count = 0;        // lane t <= S: rows r >= r0 with rp[r] <= b_t
+  uint32_t dirty_bits = 0; // bit t: tile t holds an empty row in [start, stop-1]
+  for (int rbase = r0;; rbase += kWave) {
+    const int r = rbase + lane;
+    const int p = (r <= m) ? rp[r] : INT_MAX;
+    const int q = (r < m) ? rp[r + 1] : INT_MAX;
+    if (r < m && q > p && p >= b0 && p < bS) {
+      const int off = p - b0;
+      atomicOr(&mask[off >> 5], 1u << (off & 31));
+    }
+    // an empty row at position p lies in rows start..stop-1 of the tile t
+    // with b_t < p <= b_{t+1}
+    const int te = (r < m && q == p && p > b0 && p <= bS) ? (p - b0 - 1) / WT : -1;
+    for (int t = 0; t <= S; ++t) {
+      const int bt = __shfl(my_b, t, kWave);
+      const uint64_t bal = __ballot(p <= bt);
+      if (lane == t) my_count += __popcll(bal);
+      if (t < S && __ballot(te == t)) dirty_bits |= 1u << t;
+    }
+    const int p_last = __shfl(p, kWave - 1, kWave);
+    if (!(p_last <= bS && rbase + (kWave - 1) < m)) break;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int my_start = (lane <= S) ? r0 + my_count - 1 : 0;
+  const int my_rp = (lane <= S) ? rp[my_start] : 0;
+
+  double transmitter = 0.0;
+  double sync_v = 0.0;
+  for (int t = 0; t < S; ++t) {
+    const int64_t b64 = tb * SWT + (int64_t)t * WT;
+    if (b64 >= nnz) break;
+    const int b = (int)b64;
+    const int e = (int)min<int64_t>(b64 + WT, nnz);
+    const int start = __shfl(my_start, t, kWave);
+    const int stop = __shfl(my_start, t + 1, kWave);
+    const int rp_stop = __shfl(my_rp, t + 1, kWave);
+    const bool ends_mid = (stop < m) && (rp_stop < e);
+    const bool dirty = (dirty_bits >> t) & 1u;
+    const int64_t tile = tb * S + t;
+
+    // ---- element-wise products
+    prod_t v[W];
+    const int k0 = b + lane * W;
+    if (b + WT <= nnz) {
+      int c[W];
+      prod_t av[W];
+      load_cols<W>(col, k0, c);
+      load_vals<W>(val, k0, av);
+#pragma unroll
+      for (int i = 0; i < W; ++i) v[i] = av[i] * (prod_t)x[c[i]];
+    } else {
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        const int k = k0 + i;
+        v[i] = (k < nnz) ? (prod_t)scalar_val(val, k) * (prod_t)x[col[k]] : (prod_t)0;
+      }
+    }
+
+    // ---- this lane's W descriptor bits; the tile's first bit is forced
+    uint32_t hb = (mask[t * WPT + ((lane * W) >> 5)] >> ((lane * W) & 31)) & LOW;
+    const bool bit0 = __shfl((int)hb, 0, kWave) & 1;
+    if (lane == 0) hb |= 1u;
+    const double tx = bit0 ? 0.0 : transmitter;  // carry into a tile that starts mid-row
+    if (DEBUG) {
+      for (int w = lane; w < WPT; w += kWave) {
+        uint32_t word = mask[t * WPT + w];
+        if (w == 0) word |= 1u;
+        a.dbg_heads[tile * WPT + w] = word;
+      }
+      if (lane == 0) {
+        a.dbg_start[tile] = start;
+        a.dbg_dirty[tile] = dirty ? 1 : 0;
+      }
+    }
+
+    // ---- per-lane segmented reduction: the open (last) segment of the lane
+    Acc<DT> run;
+    run.zero();
+    bool seen = false;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if ((hb >> i) & 1u) { seen = true; run.zero(); }
+      run.add(v[i]);
+    }
+    // ---- 64-lane segmented inclusive scan of (open segment, has head)
+    Acc<DT> inc = run;
+    int f = seen ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const Acc<DT> up = inc.shfl_up(d);
+      const int fu = __shfl_up(f, d, kWave);
+      if (lane >= d) {
+        if (!f) inc.prepend(up);
+        f |= fu;
+      }
+    }
+    Acc<DT> carry = inc.shfl_up(1);
+    if (lane == 0) carry.zero();
+
+    // ---- exclusive scan of head counts: compact rank of each partial
+    const int c_heads = __popc(hb);
+    int incl = c_heads;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int up = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += up;
+    }
+    const int cnt = __shfl(incl, kWave - 1, kWave);
+    int rank = incl - c_heads;
+
+    // ---- emit: the partial of segment q completes at head q+1 (or the end)
+    double v0 = 0.0, vlast = 0.0;
+    Acc<DT> cur = carry;
+    auto emit = [&](int qq, const Acc<DT> &s) {
+      const double value = s.value() + (qq == 0 ? tx : 0.0);
+      if (qq == 0) v0 = value;
+      const bool last = (qq == cnt - 1);
+      if (last) vlast = value;
+      const int idx = (last && ends_mid) ? stop : start + qq;
+      if (!(qq == 0 && start == r0) && (unsigned)idx < (unsigned)m) y[idx] = (y_t)value;
+    };
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if ((hb >> i) & 1u) {
+        if (rank > 0) emit(rank - 1, cur);
+        ++rank;
+        cur.zero();
+      }
+      cur.add(v[i]);
+    }
+    if (lane == kWave - 1) emit(cnt - 1, cur);
+
+    // rank 0 is emitted by the first lane whose inclusive head count reaches
+    // 2, or by the last lane when the tile has a single segment
+    const uint64_t bal2 = __ballot(incl >= 2);
+    const int l0 = bal2 ? (__ffsll((unsigned long long)bal2) - 1) : (kWave - 1);
+    const double v0u = __shfl(v0, l0, kWave);
+    if (start == r0) sync_v = v0u;
+    const double vlast_u = __shfl(vlast, kWave - 1, kWave);
+    transmitter = ends_mid ? vlast_u : 0.0;
+
+    // ---- dirty tile: label it for the re-arrangement
+    if (dirty && lane == 0) {
+      const int pos = atomicAdd(&a.counters[0], 1);
+      if (pos < a.n_tiles) a.speculator[pos] = make_int4(start, stop, (int)tile, 0);
+    }
+  }
+  if (lane == 0) {
+    a.sync_idx[tb] = r0;
+    a.sync_val[tb] = sync_v;
+  }
+}
+
+// ---------------------------------------------------------------- stage 2
+
+struct FixupArgs {
+  const int32_t *row_ptr;
+  void *y;
+  int32_t m;
+  int32_t nnz;
+  int32_t WT;
+  int64_t SWT;
+  int64_t n_bunches;
+  int64_t n_tiles;
+  int *counters;
+  const int4 *speculator;
+  const int32_t *sync_idx;
+  const double *sync_val;
+};
+
+template <typename YT>
+__global__ __launch_bounds__(256) void sss_fixup(FixupArgs a) {
+  extern __shared__ unsigned char lds_raw[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.WT;
+  const int32_t *__restrict__ rp = a.row_ptr;
+  YT *y = static_cast<YT *>(a.y);
+  const int n_dirty = (int)min<int64_t>(
+      __hip_atomic_load(&a.counters[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.n_tiles);
+
+  // (1) re-arrange each dirty tile: its partials 1.. sit at y[start+1..]; the
+  // k-th non-empty row strictly between start and stop receives partial k,
+  // the empty rows there receive 0.  Only rows strictly inside the tile.
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t ent = wave; ent < n_dirty; ent += n_waves) {
+    const int4 s = a.speculator[ent];
+    const int start = s.x, stop = s.y;
+    const int n_slots = min(stop - start - 1, a.WT - 1);
+    for (int i = lane; i < n_slots; i += kWave) slots[i] = y[start + 1 + i];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int base = 0;
+    for (int rb = start + 1; rb < stop; rb += kWave) {
+      const int r = rb + lane;
+      const bool in = r < stop;
+      const bool ne = in && (rp[r] != rp[r + 1]);
+      const uint64_t bal = __ballot(ne);
+      const int before = __popcll(bal & ((1ull << lane) - 1ull));
+      if (in) y[r] = ne ? slots[min(base + before, max(n_slots - 1, 0))] : (YT)0;
+      base += __popcll(bal);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+
+  // (2) synchronizer carries: for each run of bunches whose first row is the
+  // same row r, add their first-segment sums to y[r] in bunch order, in
+  // double.  y[r] holds the part of r computed before the run, unless row r
+  // begins exactly where the run's first bunch begins.
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_thr = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t tb = tid; tb < a.n_bunches; tb += n_thr) {
+    const int idx = a.sync_idx[tb];
+    if (tb > 0 && a.sync_idx[tb - 1] == idx) continue;
+    double s = 0.0;
+    for (int64_t t2 = tb; t2 < a.n_bunches && a.sync_idx[t2] == idx; ++t2) s += a.sync_val[t2];
+    const bool fresh = (int64_t)rp[idx] == tb * a.SWT;
+    y[idx] = fresh ? (YT)s : (YT)((double)y[idx] + s);
+  }
+
+  // (3) rows before the first tile's start row are empty and covered by no tile
+  const int r_first = a.n_bunches > 0 ? a.sync_idx[0] : a.m;
+  for (int64_t r = tid; r < r_first; r += n_thr) y[r] = (YT)0;
+
+  // the last block to finish resets the dirty counter for the next call
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&a.counters[1], 1);
+    if (prev == (int)gridDim.x - 1) {
+      a.counters[2] = n_dirty;
+      a.counters[0] = 0;
+      a.counters[1] = 0;
+      __threadfence();
+    }
+  }
+}
+
+template <typename YT>
+__global__ void sss_fill_zero(YT *y, int64_t m) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (YT)0;
+}
+
+__global__ void sss_validate_kernel(const int32_t *rp, const int32_t *col, int64_t m, int64_t n, int64_t nnz,
+                                    int *bad) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+  if (tid == 0 && (rp[0] != 0 || (int64_t)rp[m] != nnz)) atomicOr(bad, 1);
+  for (int64_t i = tid; i < m; i += nt)
+    if (rp[i] > rp[i + 1]) atomicOr(bad, 2);
+  for (int64_t k = tid; k < nnz; k += nt)
+    if (col[k] < 0 || (int64_t)col[k] >= n) atomicOr(bad, 4);
+}
+
+// ---------------------------------------------------------------- host side
+
+int default_W(int dt) { return dt == SSS_F64 ? 8 : 16; }
+int default_S(int dt) { return dt == SSS_F64 ? 5 : 2; }
+constexpr int kDefaultB = 2;
+constexpr int kMaxS = 16;
+
+bool dtype_ok(int dt) { return dt == SSS_F64 || dt == SSS_F32 || dt == SSS_BF16; }
+size_t y_size(int dt) { return dt == SSS_F64 ? 8 : 4; }
+
+using Stage1Fn = void (*)(Stage1Args);
+
+template <int DT, int W>
+Stage1Fn pick_dbg(bool dbg) { return dbg ? sss_stage1<DT, W, true> : sss_stage1<DT, W, false>; }
+
+template <int DT>
+Stage1Fn pick_w(int W, bool dbg) {
+  switch (W) {
+    case 4: return pick_dbg<DT, 4>(dbg);
+    case 8: return pick_dbg<DT, 8>(dbg);
+    case 16: return pick_dbg<DT, 16>(dbg);
+    default: return nullptr;
+  }
+}
+
+Stage1Fn pick_stage1(int dt, int W, bool dbg) {
+  switch (dt) {
+    case SSS_F64: return pick_w<SSS_F64>(W, dbg);
+    case SSS_F32: return pick_w<SSS_F32>(W, dbg);
+    case SSS_BF16: return pick_w<SSS_BF16>(W, dbg);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+struct sss_plan_s {
+  int device = 0;
+  int64_t m = 0, n = 0, nnz = 0;
+  int dt = SSS_F64;
+  int W = 8, S = 5, B = 2;
+  int debug = 0;
+  int64_t n_tiles = 0, n_bunches = 0;
+  void *aux = nullptr;
+  int *counters = nullptr;
+  int4 *speculator = nullptr;
+  int32_t *sync_idx = nullptr;
+  double *sync_val = nullptr;
+  int32_t *dbg_start = nullptr;
+  int32_t *dbg_dirty = nullptr;
+  uint32_t *dbg_heads = nullptr;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int plan_alloc(sss_plan p) {
+  const int WT = p->W * kWave;
+  p->n_tiles = p->nnz > 0 ? (p->nnz + WT - 1) / WT : 0;
+  const int64_t SWT = (int64_t)p->S * WT;
+  p->n_bunches = p->nnz > 0 ? (p->nnz + SWT - 1) / SWT : 0;
+  const int64_t nt = p->n_tiles, nb = p->n_bunches;
+  size_t off = 0;
+  const size_t o_cnt = off; off = align256(off + 16);
+  const size_t o_spec = off; off = align256(off + sizeof(int4) * (size_t)(nt + 1));
+  const size_t o_sidx = off; off = align256(off + sizeof(int32_t) * (size_t)(nb + 1));
+  const size_t o_sval = off; off = align256(off + sizeof(double) * (size_t)(nb + 1));
+  size_t o_ds = 0, o_dd = 0, o_dh = 0;
+  if (p->debug) {
+    o_ds = off; off = align256(off + sizeof(int32_t) * (size_t)(nt + 1));
+    o_dd = off; off = align256(off + sizeof(int32_t) * (size_t)(nt + 1));
+    o_dh = off; off = align256(off + sizeof(uint32_t) * (size_t)(nt + 1) * (WT / 32));
+  }
+  SSS_HIP(hipMalloc(&p->aux, off));
+  SSS_HIP(hipMemset(p->aux, 0, off));
+  char *base = static_cast<char *>(p->aux);
+  p->counters = reinterpret_cast<int *>(base + o_cnt);
+  p->speculator = reinterpret_cast<int4 *>(base + o_spec);
+  p->sync_idx = reinterpret_cast<int32_t *>(base + o_sidx);
+  p->sync_val = reinterpret_cast<double *>(base + o_sval);
+  if (p->debug) {
+    p->dbg_start = reinterpret_cast<int32_t *>(base + o_ds);
+    p->dbg_dirty = reinterpret_cast<int32_t *>(base + o_dd);
+    p->dbg_heads = reinterpret_cast<uint32_t *>(base + o_dh);
+  }
+  SSS_HIP(hipDeviceSynchronize());
+  return SSS_OK;
+}
+
+bool misaligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
+
+int launch(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x, void *y,
+           hipStream_t stream) {
+  if (p->m == 0) return SSS_OK;
+  if (!row_ptr || !y) return SSS_ERR_INVALID_VALUE;
+  if (p->nnz == 0) {
+    const int blocks = (int)std::min<int64_t>((p->m + 255) / 256, 4096);
+    if (p->dt == SSS_F64)
+      hipLaunchKernelGGL(sss_fill_zero<double>, dim3(blocks), dim3(256), 0, stream, (double *)y, p->m);
+    else
+      hipLaunchKernelGGL(sss_fill_zero<float>, dim3(blocks), dim3(256), 0, stream, (float *)y, p->m);
+    SSS_HIP(hipGetLastError());
+    return SSS_OK;
+  }
+  if (!col || !val || !x) return SSS_ERR_INVALID_VALUE;
+  if (misaligned(col) || misaligned(val)) return SSS_ERR_INVALID_VALUE;
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
+
+  Stage1Fn k1 = pick_stage1(p->dt, p->W, p->debug != 0);
+  if (!k1) return SSS_ERR_UNSUPPORTED;
+  const int WT = p->W * kWave;
+  Stage1Args a1;
+  a1.row_ptr = row_ptr; a1.col = col; a1.val = val; a1.x = x; a1.y = y;
+  a1.m = (int32_t)p->m; a1.nnz = (int32_t)p->nnz; a1.S = p->S; a1.n_bunches = p->n_bunches; a1.n_tiles = p->n_tiles;
+  a1.counters = p->counters; a1.speculator = p->speculator; a1.sync_idx = p->sync_idx; a1.sync_val = p->sync_val;
+  a1.dbg_start = p->dbg_start; a1.dbg_dirty = p->dbg_dirty; a1.dbg_heads = p->dbg_heads;
+  const int64_t blocks1 = (p->n_bunches + p->B - 1) / p->B;
+  const size_t lds1 = (size_t)p->B * p->S * (WT / 32) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k1, dim3((unsigned)blocks1), dim3(p->B * kWave), lds1, stream, a1);
+  SSS_HIP(hipGetLastError());
+
+  FixupArgs a2;
+  a2.row_ptr = row_ptr; a2.y = y; a2.m = (int32_t)p->m; a2.nnz = (int32_t)p->nnz; a2.WT = WT;
+  a2.SWT = (int64_t)p->S * WT; a2.n_bunches = p->n_bunches; a2.n_tiles = p->n_tiles; a2.counters = p->counters;
+  a2.speculator = p->speculator; a2.sync_idx = p->sync_idx; a2.sync_val = p->sync_val;
+  int64_t blocks2 = std::max<int64_t>((p->n_tiles + 3) / 4, (p->n_bunches + 255) / 256);
+  blocks2 = std::max<int64_t>(1, std::min<int64_t>(blocks2, 2048));
+  const size_t lds2 = 4 * (size_t)WT * y_size(p->dt);
+  if (p->dt == SSS_F64)
+    hipLaunchKernelGGL(sss_fixup<double>, dim3((unsigned)blocks2), dim3(256), lds2, stream, a2);
+  else
+    hipLaunchKernelGGL(sss_fixup<float>, dim3((unsigned)blocks2), dim3(256), lds2, stream, a2);
+  SSS_HIP(hipGetLastError());
+  return SSS_OK;
+}
+
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int64_t, int64_t, int64_t>, sss_plan> g_cache;
+
+}  // namespace
+
+extern "C" {
+
+int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, sss_dtype dt,
+                             const sss_plan_opts *opts, void *stream, sss_plan *out) {
+  (void)row_ptr;
+  (void)stream;
+  if (!out) return SSS_ERR_INVALID_VALUE;
+  *out = nullptr;
+  if (m < 0 || n < 0 || nnz < 0 || m >= INT_MAX || n >= INT_MAX || nnz >= INT_MAX) return SSS_ERR_INVALID_VALUE;
+  if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
+  sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
+  if (opts) o = *opts;
+  if (o.mode != SSS_MODE_FIXED) return SSS_ERR_UNSUPPORTED;
+  const int W = o.W ? o.W : default_W(dt);
+  const int S = o.S ? o.S : default_S(dt);
+  const int B = o.B ? o.B : kDefaultB;
+  if (!(W == 4 || W == 8 || W == 16)) return SSS_ERR_UNSUPPORTED;
+  if (S < 1 || S > kMaxS || B < 1 || B > 4) return SSS_ERR_INVALID_VALUE;
+  sss_plan p = new sss_plan_s();
+  p->m = m; p->n = n; p->nnz = nnz; p->dt = dt; p->W = W; p->S = S; p->B = B; p->debug = o.debug ? 1 : 0;
+  int rc = SSS_OK;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
+  if (rc == SSS_OK) rc = plan_alloc(p);
+  if (rc != SSS_OK) {
+    if (p->aux) (void)hipFree(p->aux);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return SSS_OK;
+}
+
+int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x,
+                         void *y, void *stream) {
+  if (!p) return SSS_ERR_INVALID_VALUE;
+  return launch(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, const double *val,
+                 const double *x, double *y, void *stream) {
+  if (m < 0 || n < 0 || nnz < 0) return SSS_ERR_INVALID_VALUE;
+  if (m == 0) return SSS_OK;
+  int dev = 0;
+  SSS_HIP(hipGetDevice(&dev));
+  sss_plan p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto key = std::make_tuple(dev, m, n, nnz);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      p = it->second;
+    } else {
+      const int rc = sss_csr_spmv_plan_create(m, n, nnz, row_ptr, SSS_F64, nullptr, stream, &p);
+      if (rc != SSS_OK) return rc;
+      g_cache[key] = p;
+    }
+  }
+  return launch(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sss_plan_destroy(sss_plan p) {
+  if (!p) return SSS_OK;
+  int rc = SSS_OK;
+  if (p->aux) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipFree(p->aux);
+    if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
+  }
+  delete p;
+  return rc;
+}
+
+int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t *n_bunches) {
+  if (!p) return SSS_ERR_INVALID_VALUE;
+  if (W) *W = p->W;
+  if (S) *S = p->S;
+  if (B) *B = p->B;
+  if (n_tiles) *n_tiles = p->n_tiles;
+  if (n_bunches) *n_bunches = p->n_bunches;
+  return SSS_OK;
+}
+
+int sss_validate_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, void *stream) {
+  if (m < 0 || n < 0 || nnz < 0) return SSS_ERR_INVALID_VALUE;
+  if (!row_ptr || (nnz > 0 && !col)) return SSS_ERR_INVALID_VALUE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int *d_bad = nullptr;
+  SSS_HIP(hipMalloc(&d_bad, sizeof(int)));
+  int rc = SSS_OK;
+  hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(int), s);
+  if (e == hipSuccess) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((std::max(m, nnz) + 255) / 256, 4096));
+    hipLaunchKernelGGL(sss_validate_kernel, dim3(blocks), dim3(256), 0, s, row_ptr, col, m, n, nnz, d_bad);
+    e = hipGetLastError();
+  }
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
+  (void)hipFree(d_bad);
+  if (rc == SSS_OK && bad) rc = SSS_ERR_INVALID_CSR;
+  return rc;
+}
+
+int sss_plan_debug_size(sss_plan p, size_t *bytes) {
+  if (!p || !bytes) return SSS_ERR_INVALID_VALUE;
+  const size_t wpt = (size_t)p->W * kWave / 32;
+  *bytes = 4 * sizeof(int64_t) + (size_t)p->n_tiles * (2 * sizeof(int32_t) + wpt * sizeof(uint32_t)) +
+           (size_t)p->n_tiles * 4 * sizeof(int32_t) + (size_t)p->n_bunches * (sizeof(int32_t) + sizeof(double));
+  return SSS_OK;
+}
+
+int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes) {
+  size_t need = 0;
+  int rc = sss_plan_debug_size(p, &need);
+  if (rc != SSS_OK) return rc;
+  if (!host_buf || bytes < need) return SSS_ERR_INVALID_VALUE;
+  SSS_HIP(hipDeviceSynchronize());
+  std::memset(host_buf, 0, need);
+  int cnt[4] = {0, 0, 0, 0};
+  SSS_HIP(hipMemcpy(cnt, p->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+  const int64_t nt = p->n_tiles, nb = p->n_bunches;
+  const int64_t wpt = (int64_t)p->W * kWave / 32;
+  int64_t *hdr = static_cast<int64_t *>(host_buf);
+  hdr[0] = nt; hdr[1] = nb; hdr[2] = cnt[2]; hdr[3] = wpt;
+  char *cur = reinterpret_cast<char *>(hdr + 4);
+  if (p->debug && nt > 0) {
+    SSS_HIP(hipMemcpy(cur, p->dbg_start, nt * sizeof(int32_t), hipMemcpyDeviceToHost));
+    SSS_HIP(hipMemcpy(cur + nt * sizeof(int32_t), p->dbg_dirty, nt * sizeof(int32_t), hipMemcpyDeviceToHost));
+    SSS_HIP(hipMemcpy(cur + 2 * nt * sizeof(int32_t), p->dbg_heads, nt * wpt * sizeof(uint32_t),
+                      hipMemcpyDeviceToHost));
+  }
+  cur += nt * (2 * sizeof(int32_t) + wpt * sizeof(uint32_t));
+  if (cnt[2] > 0) SSS_HIP(hipMemcpy(cur, p->speculator, (size_t)cnt[2] * sizeof(int4), hipMemcpyDeviceToHost));
+  cur += nt * 4 * sizeof(int32_t);
+  if (nb > 0) {
+    SSS_HIP(hipMemcpy(cur, p->sync_idx, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    SSS_HIP(hipMemcpy(cur + nb * sizeof(int32_t), p->sync_val, nb * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return SSS_OK;
+}
+
+const char *sss_status_string(int status) {
+  switch (status) {
+    case SSS_OK: return "ok";
+    case SSS_ERR_INVALID_VALUE: return "invalid value";
+    case SSS_ERR_UNSUPPORTED: return "unsupported dtype or parameters";
+    case SSS_ERR_PLAN_MISMATCH: return "plan does not match the call";
+    case SSS_ERR_HIP: return "HIP runtime error";
+    case SSS_ERR_INVALID_CSR: return "malformed CSR matrix";
+    default: return "unknown status";
+  }
+}
+
+const char *sss_last_hip_error(void) { return hipGetErrorString(g_last_hip); }
+
+const char *sss_version(void) { return "sss-spmv 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+"""Python binding of libsss (speculative segmented sum CSR SpMV on gfx950).
+
+Argument marshalling only: every step of the SpMV runs in the HIP kernels of
+libsss.so.  PyTorch supplies device memory and streams.  If the library is
+not built, importing works but every call raises ``SSSLibraryMissing`` --
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsss.so")
+
+F64, F32, BF16 = 0, 1, 2
+MODE_SELECTOR, MODE_GRID, MODE_FIXED = 0, 1, 2
+_DTYPES = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+_XTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
+_VALTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+
+STATUS = {0: "ok", -1: "invalid value", -2: "unsupported", -3: "plan mismatch", -4: "HIP error",
+          -5: "invalid CSR"}
+
+
+class SSSLibraryMissing(RuntimeError):
+    pass
+
+
+class SSSError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = f"{what}: {STATUS.get(status, status)}"
+        if status == -4 and _lib is not None:
+            msg += f" ({_lib.sss_last_hip_error().decode()})"
+        super().__init__(msg)
+        self.status = status
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int), ("B", ctypes.c_int),
+                ("debug", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsss.so (once).  Raises SSSLibraryMissing if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SSSLibraryMissing(f"{LIB_PATH} is not built; run paper_1504_06474_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.sss_csr_spmv_plan_create.argtypes = [I64, I64, I64, P, I, ctypes.POINTER(PlanOpts), P,
+                                               ctypes.POINTER(P)]
+        L.sss_csr_spmv_execute.argtypes = [P, P, P, P, P, P, P]
+        L.sss_csr_spmv.argtypes = [I64, I64, I64, P, P, P, P, P, P]
+        L.sss_plan_destroy.argtypes = [P]
+        L.sss_plan_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                                    ctypes.POINTER(I64), ctypes.POINTER(I64)]
+        L.sss_validate_csr.argtypes = [I64, I64, I64, P, P, P]
+        L.sss_plan_debug_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        L.sss_plan_debug_dump.argtypes = [P, P, ctypes.c_size_t]
+        L.sss_status_string.argtypes = [I]
+        L.sss_status_string.restype = ctypes.c_char_p
+        L.sss_last_hip_error.restype = ctypes.c_char_p
+        L.sss_version.restype = ctypes.c_char_p
+        for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_plan_destroy",
+                  "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump"):
+            getattr(L, f).restype = I
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SSSError(rc, what)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if t.device.type != "cuda":
+        raise ValueError("tensors must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return t.data_ptr() if t.numel() else None
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Plan:
+    """A plan for y = A x on an m x n matrix with nnz nonzeros (sss_csr_spmv_plan_create)."""
+
+    def __init__(self, m: int, n: int, nnz: int, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0,
+                 debug: bool = False, mode: int = MODE_FIXED, row_ptr: Optional[torch.Tensor] = None,
+                 stream=None):
+        L = lib()
+        self.m, self.n, self.nnz = int(m), int(n), int(nnz)
+        self.dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+        opts = PlanOpts(mode, W, S, B, 1 if debug else 0)
+        h = ctypes.c_void_p()
+        rc = L.sss_csr_spmv_plan_create(self.m, self.n, self.nnz, _ptr(row_ptr), self.dt, ctypes.byref(opts),
+                                        _stream(stream), ctypes.byref(h))
+        _check(rc, "sss_csr_spmv_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        W, S, B = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        nt, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sss_plan_info(self._h, ctypes.byref(W), ctypes.byref(S), ctypes.byref(B), ctypes.byref(nt),
+                                   ctypes.byref(nb)), "sss_plan_info")
+        return {"W": W.value, "S": S.value, "B": B.value, "n_tiles": nt.value, "n_bunches": nb.value}
+
+    def execute(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,
+                y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if y is None:
+            y = torch.empty(self.m, dtype=_XTYPE[self.dt], device=x.device)
+        if val.dtype != _VALTYPE[self.dt] or x.dtype != _XTYPE[self.dt] or y.dtype != _XTYPE[self.dt]:
+            raise TypeError("val/x/y dtypes do not match the plan")
+        if row_ptr.dtype != torch.int32 or col.dtype != torch.int32:
+            raise TypeError("row_ptr and col must be int32")
+        if row_ptr.numel() != self.m + 1 or col.numel() < self.nnz or val.numel() < self.nnz:
+            raise ValueError("array sizes do not match the plan")
+        if x.numel() < self.n or y.numel() < self.m:
+            raise ValueError("x or y too short")
+        rc = lib().sss_csr_spmv_execute(self._h, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
+                                        _stream(stream))
+        _check(rc, "sss_csr_spmv_execute")
+        return y
+
+    def debug_dump(self) -> dict:
+        L = lib()
+        size = ctypes.c_size_t()
+        _check(L.sss_plan_debug_size(self._h, ctypes.byref(size)), "sss_plan_debug_size")
+        buf = np.zeros(size.value, dtype=np.uint8)
+        _check(L.sss_plan_debug_dump(self._h, buf.ctypes.data, size.value), "sss_plan_debug_dump")
+        hdr = buf[:32].view(np.int64)
+        nt, nb, nd, wpt = (int(v) for v in hdr)
+        o = 32
+        tile_start = buf[o:o + 4 * nt].view(np.int32); o += 4 * nt
+        tile_dirty = buf[o:o + 4 * nt].view(np.int32); o += 4 * nt
+        heads = buf[o:o + 4 * nt * wpt].view(np.uint32).reshape(nt, wpt); o += 4 * nt * wpt
+        spec = buf[o:o + 16 * nt].view(np.int32).reshape(nt, 4)[:nd]; o += 16 * nt
+        sync_idx = buf[o:o + 4 * nb].view(np.int32); o += 4 * nb
+        sync_val = buf[o:o + 8 * nb].view(np.float64)
+        return {"n_tiles": nt, "n_bunches": nb, "dirty_count": nd, "tile_start": tile_start.copy(),
+                "tile_dirty": tile_dirty.copy(), "heads": heads.copy(), "speculator": spec.copy(),
+                "sync_idx": sync_idx.copy(), "sync_val": sync_val.copy()}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _check(_lib.sss_plan_destroy(self._h), "sss_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def csr_spmv(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,
+             y: Optional[torch.Tensor] = None, n: Optional[int] = None, stream=None) -> torch.Tensor:
+    """The one-call double-precision form, sss_csr_spmv (internal plan cache)."""
+    m = row_ptr.numel() - 1
+    n = x.numel() if n is None else int(n)
+    nnz = val.numel()
+    if y is None:
+        y = torch.empty(m, dtype=torch.float64, device=x.device)
+    for t in (val, x, y):
+        if t.dtype != torch.float64:
+            raise TypeError("sss_csr_spmv is the double-precision form")
+    rc = lib().sss_csr_spmv(m, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y), _stream(stream))
+    _check(rc, "sss_csr_spmv")
+    return y
+
+
+def validate_csr(row_ptr: torch.Tensor, col: torch.Tensor, n: int, stream=None) -> bool:
+    m = row_ptr.numel() - 1
+    rc = lib().sss_validate_csr(m, n, col.numel(), _ptr(row_ptr), _ptr(col), _stream(stream))
+    if rc == -5:
+        return False
+    _check(rc, "sss_validate_csr")
+    return True
+
+
+def version() -> str:
+    return lib().sss_version().decode()

@@ -1,0 +1,50 @@
+"""The C ABI: the built library loads and exports every entry point that
+include/sss.h declares.  No GPU needed (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "sss.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sss_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for s in ("sss_csr_spmv", "sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_plan_destroy"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1504_06474_amd import sss
+    L = sss.lib()
+    missing = [s for s in declared_symbols() if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    from paper_1504_06474_amd import sss
+    L = sss.lib()
+    assert L.sss_status_string(0) == b"ok"
+    assert L.sss_status_string(-5) == b"malformed CSR matrix"
+    assert b"gfx950" in L.sss_version()
+
+
+def test_host_side_argument_checks():
+    """Plan creation rejects bad sizes and parameters before any device call."""
+    from paper_1504_06474_amd import sss
+    L = sss.lib()
+    h = ctypes.c_void_p()
+    bad = sss.PlanOpts(sss.MODE_FIXED, 5, 1, 1, 0)  # W = 5 is not built
+    assert L.sss_csr_spmv_plan_create(10, 10, 10, None, 0, ctypes.byref(bad), None, ctypes.byref(h)) == -2
+    assert L.sss_csr_spmv_plan_create(-1, 10, 10, None, 0, None, None, ctypes.byref(h)) == -1
+    assert L.sss_csr_spmv_plan_create(10, 10, 10, None, 7, None, None, ctypes.byref(h)) == -2
+    bad_s = sss.PlanOpts(sss.MODE_FIXED, 8, 0, 9, 0)  # B = 9 out of range
+    assert L.sss_csr_spmv_plan_create(10, 10, 10, None, 0, ctypes.byref(bad_s), None, ctypes.byref(h)) == -1
+    assert L.sss_csr_spmv_execute(None, None, None, None, None, None, None) == -1

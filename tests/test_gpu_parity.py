@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Double precision: per-row tolerance 1e-12 * (|A||x|)_i; integer-valued inputs
+bit-exact.  The debug dump of stage 1 (tile start rows, segment descriptors,
+dirty tiles, speculator, synchronizer) must equal the oracle's definitions
+exactly, at T = 64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import csrgen
+import oracle
+from oracle import speculative as sp
+from helpers import note, to_dev, assert_f64_parity, assert_exact, csr_from_lengths
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1504_06474_amd import sss
+    sss.lib()  # fails loudly if the library is not built
+    return torch
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    note(f"[gpu-test] {request.node.nodeid}")
+    yield
+
+
+def run_plan(torch, A, x, W=0, S=0, B=0, debug=False, dtype=None):
+    from paper_1504_06474_amd import sss
+    dtype = dtype or torch.float64
+    xdt = torch.float64 if dtype == torch.float64 else torch.float32
+    rp, col, v, xx = to_dev(A, x, val_dtype=dtype, x_dtype=xdt)
+    plan = sss.Plan(A.m, A.n, A.nnz, dtype=dtype, W=W, S=S, B=B, debug=debug)
+    y = plan.execute(rp, col, v, xx)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy(), plan
+
+
+def test_config1_f64_default(torch_cuda):
+    A, x = csrgen.config1()
+    note(f"  poisson4096 nnz={A.nnz}")
+    y, _ = run_plan(torch_cuda, A, x)
+    ref = oracle.spmv(A.row_ptr, A.col, A.val, x)
+    assert_f64_parity(y, ref, oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
+
+
+@pytest.mark.parametrize("W", [4, 8, 16])
+@pytest.mark.parametrize("S", [1, 2, 5, 8])
+@pytest.mark.parametrize("B", [1, 4])
+def test_config1_integer_exact_all_params(torch_cuda, W, S, B):
+    A, x = csrgen.config1(int_valued=True)
+    y, _ = run_plan(torch_cuda, A, x, W=W, S=S, B=B)
+    assert_exact(y, oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+EDGE = {
+    "single_entry": ([1], 1),
+    "identity_1000": ([1] * 1000, 1000),
+    "all_empty": ([0] * 300, 50),
+    "leading_trailing_empty": ([0] * 700 + [3, 5, 1] * 200 + [0] * 900, 400),
+    "long_row_many_bunches": ([2] * 50 + [150_000] + [1] * 3000 + [0] * 10 + [40_000], 200_000),
+    "empty_run_100k_inside_tile": ([5] * 10 + [0] * 100_000 + [7] * 10, 100),
+    "rows_of_one_tile": ([512] * 30 + [0] + [512] * 30, 1024),
+    "rows_of_two_tiles_with_empties": ([1024, 0, 0, 1024, 0, 1024] * 10, 2048),
+    "alternating_empty": ([1, 0] * 20_000, 64),
+    "dense_rows": ([4096] * 64, 4096),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+@pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
+def test_edge_matrices_integer_exact(torch_cuda, name, WS):
+    lengths, n = EDGE[name]
+    A, x = csr_from_lengths(lengths, n, seed=len(lengths))
+    note(f"  {name} m={A.m} nnz={A.nnz} W,S={WS}")
+    y, _ = run_plan(torch_cuda, A, x, W=WS[0], S=WS[1])
+    assert_exact(y, oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+def test_m_zero_and_nnz_zero(torch_cuda):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    p = sss.Plan(0, 5, 0)
+    y = torch.empty(0, dtype=torch.float64, device="cuda")
+    p.execute(torch.zeros(1, dtype=torch.int32, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"),
+              torch.zeros(0, dtype=torch.float64, device="cuda"), torch.ones(5, dtype=torch.float64, device="cuda"), y)
+    p2 = sss.Plan(7, 5, 0)
+    y2 = torch.full((7,), 3.0, dtype=torch.float64, device="cuda")
+    p2.execute(torch.zeros(8, dtype=torch.int32, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"),
+               torch.zeros(0, dtype=torch.float64, device="cuda"), torch.ones(5, dtype=torch.float64, device="cuda"),
+               y2)
+    torch.cuda.synchronize()
+    assert y2.cpu().numpy().tolist() == [0.0] * 7
+
+
+def _check_dump(d, A, W, S, x):
+    T = 64
+    rp = A.row_ptr.astype(np.int64)
+    n_tiles = math.ceil(A.nnz / (W * T))
+    assert d["n_tiles"] == n_tiles
+    assert d["n_bunches"] == math.ceil(A.nnz / (S * W * T))
+    starts = sp.tile_starts_vec(rp, T, W)
+    assert np.array_equal(d["tile_start"], starts[:-1])
+    dirty = sp.dirty_tiles_vec(rp, T, W)
+    assert np.array_equal(d["tile_dirty"].astype(bool), dirty)
+    flags = sp.head_flags_vec(rp, T, W).reshape(n_tiles, W * T // 32, 32)
+    words = (flags.astype(np.uint64) << np.arange(32, dtype=np.uint64)).sum(axis=2).astype(np.uint32)
+    assert np.array_equal(d["heads"], words)
+    assert d["dirty_count"] == int(dirty.sum())
+    spec = {tuple(r[:3]) for r in d["speculator"]}
+    want = {(int(starts[t]), int(starts[t + 1]), t) for t in np.nonzero(dirty)[0]}
+    assert spec == want
+    assert np.array_equal(d["sync_idx"], starts[:-1][::S])
+
+
+def test_debug_dump_matches_oracle_definitions(torch_cuda):
+    A, x = csrgen.config1(int_valued=True)
+    for W, S in ((8, 5), (4, 1), (16, 2)):
+        note(f"  dump W={W} S={S}")
+        y, plan = run_plan(torch_cuda, A, x, W=W, S=S, debug=True)
+        assert_exact(y, oracle.spmv(A.row_ptr, A.col, A.val, x))
+        _check_dump(plan.debug_dump(), A, W, S, x)
+
+
+def test_debug_dump_synchronizer_matches_loop_model(torch_cuda):
+    """Synchronizer values against the step-by-step model at T = 64."""
+    A, x = csr_from_lengths([3, 0, 700, 1, 1, 0, 0, 2000, 5] * 8 + [9] * 300, 3000, seed=4)
+    W, S = 4, 2
+    y, plan = run_plan(torch_cuda, A, x, W=W, S=S, debug=True)
+    d = plan.debug_dump()
+    r1 = sp.stage_one(A.row_ptr, A.col, A.val, x, 64, W, S)
+    assert [s[0] for s in r1.synchronizer] == list(d["sync_idx"])
+    assert [s[1] for s in r1.synchronizer] == list(d["sync_val"])
+    assert d["dirty_count"] == r1.dirty_counter
+    assert {tuple(r[:3]) for r in d["speculator"]} == set(r1.speculator)
+    assert_exact(y, sp.stage_two(r1, A.row_ptr))
+
+
+def test_repeat_and_determinism(torch_cuda):
+    """The dirty counter is reset between calls; results are bitwise stable."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1()
+    rp, col, v, xx = to_dev(A, x)
+    plan = sss.Plan(A.m, A.n, A.nnz, debug=True)
+    ys = []
+    for _ in range(5):
+        ys.append(plan.execute(rp, col, v, xx).cpu().numpy())
+        d = plan.debug_dump()
+        assert d["dirty_count"] == int(sp.dirty_tiles_vec(A.row_ptr, 64, 8).sum())
+    for y in ys[1:]:
+        assert np.array_equal(y, ys[0])
+
+
+def test_one_call_form_and_validate(torch_cuda):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1(int_valued=True)
+    rp, col, v, xx = to_dev(A, x)
+    y = sss.csr_spmv(rp, col, v, xx)
+    y2 = sss.csr_spmv(rp, col, v, xx)  # cached plan
+    assert_exact(y.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+    assert torch.equal(y, y2)
+    assert sss.validate_csr(rp, col, A.n)
+    bad_col = col.clone()
+    bad_col[5] = A.n
+    assert not sss.validate_csr(rp, bad_col, A.n)
+    bad_rp = rp.clone()
+    bad_rp[10] = bad_rp[11] + 1
+    assert not sss.validate_csr(bad_rp, col, A.n)
+
+
+def test_misaligned_pointers_rejected(torch_cuda):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1()
+    rp, col, v, xx = to_dev(A, x)
+    colx = torch.empty(A.nnz + 1, dtype=torch.int32, device="cuda")
+    colx[1:] = col
+    plan = sss.Plan(A.m, A.n, A.nnz)
+    with pytest.raises(sss.SSSError):
+        plan.execute(rp, colx[1:], v, xx)
+
+
+@pytest.mark.parametrize("WS", [(8, 5), (4, 8), (16, 2)])
+def test_config2_full_size_f64(torch_cuda, WS):
+    """The 1M-row power-law matrix: every row against the oracle."""
+    A, x = _config2_cached()
+    note(f"  powerlaw1e6 nnz={A.nnz} W,S={WS}")
+    y, _ = run_plan(torch_cuda, A, x, W=WS[0], S=WS[1])
+    ref, scale = _config2_ref()
+    assert_f64_parity(y, ref, scale)
+
+
+_C2 = {}
+
+
+def _config2_cached():
+    if "A" not in _C2:
+        _C2["A"], _C2["x"] = csrgen.config2()
+    return _C2["A"], _C2["x"]
+
+
+def _config2_ref():
+    A, x = _config2_cached()
+    if "ref" not in _C2:
+        _C2["ref"] = oracle.spmv(A.row_ptr, A.col, A.val, x)
+        _C2["scale"] = oracle.abs_spmv(A.row_ptr, A.col, A.val, x)
+    return _C2["ref"], _C2["scale"]
