@@ -81,7 +81,8 @@ typedef struct sss_plan_s *sss_plan;
 /* Create a plan for an m x n matrix with nnz nonzeros of value type dt.
  * Section 3.3 sizes the auxiliary arrays it allocates: the synchronizer has
  * one entry per thread-bunch, ceil(nnz / (S W T)); the speculator one per
- * tile, ceil(nnz / (W T)); the dirty counter is one integer.
+ * tile, ceil(nnz / (W T)), here laid out as S slots per thread-bunch with a
+ * per-bunch dirty mask in place of the single global dirty counter.
  * row_ptr (device, may be NULL in FIXED mode) is read only by the GRID and
  * SELECTOR modes, on `stream`, which this call then synchronises.
  * opts may be NULL (FIXED with the defaults).  Returns the plan in *out. */
@@ -96,6 +97,20 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
  * if the plan was created on another device. */
 int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col,
                          const void *val, const void *x, void *y, void *stream);
+
+/* The two stages of execute, separately (same arguments, same stream order
+ * required: stage 2 must follow stage 1 of the same plan on the same stream,
+ * with no other call on that plan in between).
+ * Stage 1, speculative execution (Section 3.2 and the appendix algorithm's
+ * first-stage function): writes y at speculated positions, the synchronizer,
+ * the dirty counter and the speculator.  Stage 2, checking prediction
+ * (Section 3.2; the appendix's synchronization function plus the
+ * re-arrangement): adds the cross-bunch carries, moves the dirty tiles' partial
+ * sums to their rows, zeroes leading empty rows, and resets the dirty counter.
+ * They exist so that a caller can time or overlap the stages. */
+int sss_csr_spmv_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val,
+                        const void *x, void *y, void *stream);
+int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *stream);
 
 /* The one-call form of the method in double precision: y = A x with the
  * default parameters.  Keeps an internal plan per (device, m, nnz) that it
@@ -127,8 +142,8 @@ int sss_plan_debug_size(sss_plan p, size_t *bytes);
  *   int32 tile_dirty[n_tiles]          (debug plans only, else zeros)
  *   uint32 heads[n_tiles * words_per_tile]  segment descriptor bits, bit k of
  *          word w = entry 32w+k of the tile, forced first bit included
- *   int32 speculator[n_tiles * 4]      {start, stop, tile, 0}; the first
- *          dirty_count entries are valid, in the order of the atomic increments
+ *   int32 speculator[n_tiles * 4]      {start, stop, tile, 0} of every dirty
+ *          tile, in tile order; the first dirty_count entries are valid
  *   int32 sync_idx[n_bunches]
  *   double sync_val[n_bunches]
  * Section 3.2 and the appendix algorithm define these arrays. */

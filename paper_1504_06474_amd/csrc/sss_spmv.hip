@@ -18,21 +18,29 @@
 //     sum its compact rank q, and the store of partial q to y[start + q].
 //     The bunch's first segment goes to the synchronizer instead; a tile that
 //     ends inside row `stop` hands its last partial to the next tile through
-//     the transmitter.  Dirty tiles are appended to the speculator with one
-//     atomic increment of the dirty counter.
+//     the transmitter.  Dirty tiles are recorded, as <start, stop, tile>, in
+//     the bunch's own speculator slots, with a per-bunch dirty mask.
 // Stage 2 (Section 3.2, checking prediction; the paper runs it on a CPU core)
 // is one device kernel with three independent parts: the synchronizer carries
-// (one thread per run of bunches sharing a first row), the re-arrangement of
-// each dirty tile's partial sums to its non-empty rows (one wavefront per
-// speculator entry), and zeroing the leading empty rows no tile covers.
+// (one thread per run of bunches sharing a first row; the wavefront for long
+// runs), the re-arrangement of each dirty tile's partial sums to its non-empty
+// rows (one wavefront per thread-bunch), and zeroing the leading empty rows no
+// tile covers.
 //
-// Difference from the paper's listing, on purpose: a dirty tile that ends
-// inside row `stop` also passes its last partial on through the transmitter
-// and writes it at y[stop] (its true row), where the listing clears the
-// transmitter and leaves that partial to the re-arrangement.  The result is
-// the same sum; the gain is that the re-arrangement then only touches rows
-// strictly inside dirty tiles, so all three parts of stage 2 are disjoint and
-// run concurrently in one launch, with no ordering between them.
+// Differences from the paper's listing, on purpose:
+//  * a dirty tile that ends inside row `stop` also passes its last partial on
+//    through the transmitter and writes it at y[stop] (its true row), where
+//    the listing clears the transmitter and leaves that partial to the
+//    re-arrangement.  The result is the same sum; the gain is that the
+//    re-arrangement then only touches rows strictly inside dirty tiles, so all
+//    three parts of stage 2 are disjoint and run concurrently in one launch,
+//    with no ordering between them.
+//  * the speculator is packed per thread-bunch (S slots each, plus a dirty
+//    mask) instead of through one global atomic counter.  On a multi-die GPU a
+//    device-wide counter needs either a cross-die atomic per dirty tile and a
+//    grid-wide "last block" handshake to reset it between calls, or an extra
+//    launch; per-bunch slots need neither, and stage 2's wavefront for a bunch
+//    finds that bunch's dirty tiles directly.
 //
 // Precision: F64 sums in double.  F32/BF16 multiply in float and sum segments
 // with TwoSum-compensated float pairs; each partial is formed in double, the
@@ -47,12 +55,14 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "sss.h"
 
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kShortRun = 16;  // stage-2 carry runs up to this many bunches: one thread
 
 thread_local hipError_t g_last_hip = hipSuccess;
 
@@ -70,6 +80,29 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+#ifndef SSS_NT_LOADS
+#define SSS_NT_LOADS 0
+#endif
+#ifndef SSS_NT_STORES
+#define SSS_NT_STORES 0
+#endif
+#ifndef SSS_WAVES_PER_EU
+#define SSS_WAVES_PER_EU 0
+#endif
+
+// streaming loads of the matrix arrays (plain loads stream faster than
+// non-temporal ones on gfx950 for this lane-contiguous pattern)
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p) {
+  if constexpr (SSS_NT_LOADS) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename T>
+__device__ __forceinline__ void y_store(T v, T *p) {
+  if constexpr (SSS_NT_STORES) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 
 // ---------------------------------------------------------------- value types
 
@@ -140,7 +173,7 @@ __device__ __forceinline__ void load_cols(const int32_t *__restrict__ col, int k
   const v4i *p = reinterpret_cast<const v4i *>(col + k0);
 #pragma unroll
   for (int i = 0; i < W / 4; ++i) {
-    v4i v = __builtin_nontemporal_load(p + i);
+    v4i v = stream_load(p + i);
     c[4 * i + 0] = v.x; c[4 * i + 1] = v.y; c[4 * i + 2] = v.z; c[4 * i + 3] = v.w;
   }
 }
@@ -150,7 +183,7 @@ __device__ __forceinline__ void load_vals(const double *__restrict__ val, int k0
   const v2d *p = reinterpret_cast<const v2d *>(val + k0);
 #pragma unroll
   for (int i = 0; i < W / 2; ++i) {
-    v2d v = __builtin_nontemporal_load(p + i);
+    v2d v = stream_load(p + i);
     a[2 * i] = v.x; a[2 * i + 1] = v.y;
   }
 }
@@ -160,7 +193,7 @@ __device__ __forceinline__ void load_vals(const float *__restrict__ val, int k0,
   const v4f *p = reinterpret_cast<const v4f *>(val + k0);
 #pragma unroll
   for (int i = 0; i < W / 4; ++i) {
-    v4f v = __builtin_nontemporal_load(p + i);
+    v4f v = stream_load(p + i);
     a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
   }
 }
@@ -171,7 +204,7 @@ __device__ __forceinline__ void load_vals(const uint16_t *__restrict__ val, int 
     const v4u *p = reinterpret_cast<const v4u *>(val + k0);
 #pragma unroll
     for (int i = 0; i < W / 8; ++i) {
-      v4u v = __builtin_nontemporal_load(p + i);
+      v4u v = stream_load(p + i);
       unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -183,7 +216,7 @@ __device__ __forceinline__ void load_vals(const uint16_t *__restrict__ val, int 
     const v2u *p = reinterpret_cast<const v2u *>(val + k0);
 #pragma unroll
     for (int i = 0; i < W / 4; ++i) {
-      v2u v = __builtin_nontemporal_load(p + i);
+      v2u v = stream_load(p + i);
       a[4 * i] = bf16_to_f32(v.x & 0xffffu);
       a[4 * i + 1] = bf16_to_f32(v.x >> 16);
       a[4 * i + 2] = bf16_to_f32(v.y & 0xffffu);
@@ -219,6 +252,80 @@ __device__ __forceinline__ int wave_rightmost(const int32_t *__restrict__ rp, in
   return lo + __popcll(__ballot(pred)) - 1;
 }
 
+// ---------------------------------------------------------------- wave scans
+
+// 64-lane scans with DPP: Hillis-Steele shifts by 1, 2, 4, 8 inside each
+// 16-lane row, then row broadcasts of lane 15 (into rows 1 and 3) and lane 31
+// (into rows 2 and 3).  Lanes whose source is out of range read 0, the
+// identity of both scans below.
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL, ROWS>((int)(unsigned long long)b);
+  const int hi = dpp_i<CTRL, ROWS>((int)((unsigned long long)b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ AccD dpp_acc(const AccD &v) { AccD r; r.s = dpp_d<CTRL, ROWS>(v.s); return r; }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ AccC dpp_acc(const AccC &v) {
+  AccC r;
+  r.hi = dpp_f<CTRL, ROWS>(v.hi);
+  r.lo = dpp_f<CTRL, ROWS>(v.lo);
+  return r;
+}
+
+// one step of the segmented scan: (v, f) := (v_src, f_src) (+) (v, f), where
+// (a, fa) (+) (b, fb) = (fb ? b : a + b, fa | fb)
+template <int CTRL, int ROWS, class A>
+__device__ __forceinline__ void seg_step(A &v, int &f) {
+  const A up = dpp_acc<CTRL, ROWS>(v);
+  const int fu = dpp_i<CTRL, ROWS>(f);
+  if (!f) v.prepend(up);
+  f |= fu;
+}
+
+// inclusive segmented scan over the wave of (v, head flag)
+template <class A>
+__device__ __forceinline__ void wave_seg_scan(A &v, int &f) {
+  seg_step<kRowShr1, 0xf>(v, f);
+  seg_step<kRowShr2, 0xf>(v, f);
+  seg_step<kRowShr4, 0xf>(v, f);
+  seg_step<kRowShr8, 0xf>(v, f);
+  seg_step<kRowBcast15, 0xa>(v, f);
+  seg_step<kRowBcast31, 0xc>(v, f);
+}
+
+// inclusive integer scan over the wave
+__device__ __forceinline__ int wave_iscan(int x) {
+  x += dpp_i<kRowShr1, 0xf>(x);
+  x += dpp_i<kRowShr2, 0xf>(x);
+  x += dpp_i<kRowShr4, 0xf>(x);
+  x += dpp_i<kRowShr8, 0xf>(x);
+  x += dpp_i<kRowBcast15, 0xa>(x);
+  x += dpp_i<kRowBcast31, 0xc>(x);
+  return x;
+}
+
+// sum over the 64 lanes in a fixed tree (pairs 1 apart, 2 apart, ... 32
+// apart); every lane returns the total
+__device__ __forceinline__ double wave_sum_tree(double v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
 // ---------------------------------------------------------------- stage 1
 
 struct Stage1Args {
@@ -232,17 +339,45 @@ struct Stage1Args {
   int32_t S;
   int64_t n_bunches;
   int64_t n_tiles;
-  int *counters;        // [0] dirty counter, [1] fixup block counter, [2] last dirty count
-  int4 *speculator;     // <start, stop, tile, 0>
+  uint32_t *dirty_mask;  // per bunch: bit t set when its tile t is dirty
+  int4 *speculator;      // per bunch, S slots: <start, stop, tile, 0> of its dirty tiles, packed
   int32_t *sync_idx;
   double *sync_val;
-  int32_t *dbg_start;   // debug plans only
+  int32_t *dbg_start;    // debug plans only
   int32_t *dbg_dirty;
   uint32_t *dbg_heads;
 };
 
+// LDS words per wavefront: S tiles of descriptor bits, the dirty-tile bits
+// (padded to 2 words), then W*T double slots for one tile's compact partials.
+__host__ __device__ constexpr int stage1_lds_words(int W, int S) { return S * (W * kWave / 32) + 2 + 2 * W * kWave; }
+
+// col/val of one tile, lane-contiguous (lane j: entries [jW, jW+W)); entries
+// past nnz read as column 0 with value 0.
+template <int W, typename val_t, typename prod_t>
+__device__ __forceinline__ void load_tile(const int32_t *__restrict__ col, const val_t *__restrict__ val, int b,
+                                          int nnz, int lane, int (&c)[W], prod_t (&av)[W]) {
+  const int k0 = b + lane * W;
+  if (b + W * kWave <= nnz) {
+    load_cols<W>(col, k0, c);
+    load_vals<W>(val, k0, av);
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      const int k = k0 + i;
+      const bool in = k < nnz;
+      c[i] = in ? col[k] : 0;
+      av[i] = in ? (prod_t)scalar_val(val, k) : (prod_t)0;
+    }
+  }
+}
+
 template <int DT, int W, bool DEBUG>
-__global__ __launch_bounds__(256) void sss_stage1(Stage1Args a) {
+__global__ __launch_bounds__(256)
+#if SSS_WAVES_PER_EU
+__attribute__((amdgpu_waves_per_eu(SSS_WAVES_PER_EU, 8)))
+#endif
+void sss_stage1(Stage1Args a) {
   using val_t = typename VT<DT>::val_t;
   using x_t = typename VT<DT>::x_t;
   using y_t = typename VT<DT>::y_t;
@@ -263,22 +398,29 @@ __global__ __launch_bounds__(256) void sss_stage1(Stage1Args a) {
   const x_t *__restrict__ x = static_cast<const x_t *>(a.x);
   y_t *__restrict__ y = static_cast<y_t *>(a.y);
   const int m = a.m, nnz = a.nnz, S = a.S;
-  uint32_t *mask = lds_words + wid * (S * WPT);
+  uint32_t *mask = lds_words + wid * stage1_lds_words(W, S);
+  uint32_t *dflag = mask + S * WPT;
+  double *part = reinterpret_cast<double *>(mask + S * WPT + 2);
 
   const int64_t SWT = (int64_t)S * WT;
   const int b0 = (int)(tb * SWT);  // < nnz
   const int bS = (int)min<int64_t>(tb * SWT + SWT, nnz);
+
+  // ---- tile 0's col/val do not depend on the row structure: issue first
+  int cc[W];
+  prod_t av[W];
+  load_tile<W>(col, val, b0, nnz, lane, cc, av);
 
   // ---- tile boundary search (rightmost match) for the bunch's first row
   const int r0 = wave_rightmost(rp, m, b0, lane);
 
   // ---- descriptor, tile start rows, dirty tiles: one pass over the rows
   for (int i = lane; i < S * WPT; i += kWave) mask[i] = 0u;
+  if (lane == 0) *dflag = 0u;
   __builtin_amdgcn_wave_barrier();
 
   const int my_b = (int)min<int64_t>(tb * SWT + (int64_t)min(lane, S) * WT, nnz);
-  int my_count = 0;        // lane t <= S: rows r >= r0 with rp[r] <= b_t
-  uint32_t dirty_bits = 0; // bit t: tile t holds an empty row in [start, stop-1]
+  int my_count = 0;  // lane t <= S: rows r >= r0 with rp[r] <= b_t
   for (int rbase = r0;; rbase += kWave) {
     const int r = rbase + lane;
     const int p = (r <= m) ? rp[r] : INT_MAX;
@@ -289,19 +431,24 @@ __global__ __launch_bounds__(256) void sss_stage1(Stage1Args a) {
     }
     // an empty row at position p lies in rows start..stop-1 of the tile t
     // with b_t < p <= b_{t+1}
-    const int te = (r < m && q == p && p > b0 && p <= bS) ? (p - b0 - 1) / WT : -1;
+    if (r < m && q == p && p > b0 && p <= bS) atomicOr(dflag, 1u << ((p - b0 - 1) / WT));
     for (int t = 0; t <= S; ++t) {
       const int bt = __shfl(my_b, t, kWave);
       const uint64_t bal = __ballot(p <= bt);
       if (lane == t) my_count += __popcll(bal);
-      if (t < S && __ballot(te == t)) dirty_bits |= 1u << t;
     }
     const int p_last = __shfl(p, kWave - 1, kWave);
     if (!(p_last <= bS && rbase + (kWave - 1) < m)) break;
   }
   __builtin_amdgcn_wave_barrier();
+  const uint32_t dirty_bits = *dflag;
   const int my_start = (lane <= S) ? r0 + my_count - 1 : 0;
   const int my_rp = (lane <= S) ? rp[my_start] : 0;
+
+  // ---- x gathers of tile 0
+  prod_t xv[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) xv[i] = (prod_t)x[cc[i]];
 
   double transmitter = 0.0;
   double sync_v = 0.0;
@@ -316,28 +463,19 @@ __global__ __launch_bounds__(256) void sss_stage1(Stage1Args a) {
     const bool ends_mid = (stop < m) && (rp_stop < e);
     const bool dirty = (dirty_bits >> t) & 1u;
     const int64_t tile = tb * S + t;
+    const bool has_next = (t + 1 < S) && (b64 + WT < nnz);
 
-    // ---- element-wise products
+    // ---- prefetch the next tile's col/val; products of this tile
+    int cn[W];
+    prod_t an[W];
+    if (has_next) load_tile<W>(col, val, b + WT, nnz, lane, cn, an);
     prod_t v[W];
-    const int k0 = b + lane * W;
-    if (b + WT <= nnz) {
-      int c[W];
-      prod_t av[W];
-      load_cols<W>(col, k0, c);
-      load_vals<W>(val, k0, av);
 #pragma unroll
-      for (int i = 0; i < W; ++i) v[i] = av[i] * (prod_t)x[c[i]];
-    } else {
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        const int k = k0 + i;
-        v[i] = (k < nnz) ? (prod_t)scalar_val(val, k) * (prod_t)x[col[k]] : (prod_t)0;
-      }
-    }
+    for (int i = 0; i < W; ++i) v[i] = av[i] * xv[i];
 
     // ---- this lane's W descriptor bits; the tile's first bit is forced
     uint32_t hb = (mask[t * WPT + ((lane * W) >> 5)] >> ((lane * W) & 31)) & LOW;
-    const bool bit0 = __shfl((int)hb, 0, kWave) & 1;
+    const bool bit0 = __builtin_amdgcn_readlane((int)hb, 0) & 1;
     if (lane == 0) hb |= 1u;
     const double tx = bit0 ? 0.0 : transmitter;  // carry into a tile that starts mid-row
     if (DEBUG) {
@@ -355,78 +493,77 @@ __global__ __launch_bounds__(256) void sss_stage1(Stage1Args a) {
     // ---- per-lane segmented reduction: the open (last) segment of the lane
     Acc<DT> run;
     run.zero();
-    bool seen = false;
+    int f = 0;
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      if ((hb >> i) & 1u) { seen = true; run.zero(); }
+      if ((hb >> i) & 1u) { f = 1; run.zero(); }
       run.add(v[i]);
     }
-    // ---- 64-lane segmented inclusive scan of (open segment, has head)
-    Acc<DT> inc = run;
-    int f = seen ? 1 : 0;
+    // ---- the next tile's x gathers go out while this tile finishes
+    if (has_next) {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const Acc<DT> up = inc.shfl_up(d);
-      const int fu = __shfl_up(f, d, kWave);
-      if (lane >= d) {
-        if (!f) inc.prepend(up);
-        f |= fu;
-      }
+      for (int i = 0; i < W; ++i) { xv[i] = (prod_t)x[cn[i]]; av[i] = an[i]; }
     }
-    Acc<DT> carry = inc.shfl_up(1);
-    if (lane == 0) carry.zero();
+    // ---- wave segmented scan of the open segments; carry into each lane
+    Acc<DT> inc = run;
+    wave_seg_scan(inc, f);
+    const Acc<DT> carry = dpp_acc<kWaveShr1, 0xf>(inc);
 
     // ---- exclusive scan of head counts: compact rank of each partial
     const int c_heads = __popc(hb);
-    int incl = c_heads;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int up = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += up;
-    }
-    const int cnt = __shfl(incl, kWave - 1, kWave);
+    const int incl = wave_iscan(c_heads);
+    const int cnt = __builtin_amdgcn_readlane(incl, kWave - 1);
     int rank = incl - c_heads;
 
-    // ---- emit: the partial of segment q completes at head q+1 (or the end)
-    double v0 = 0.0, vlast = 0.0;
+    // ---- partial of segment q (completed at head q+1, or at the tile end)
+    // into LDS slot q
     Acc<DT> cur = carry;
-    auto emit = [&](int qq, const Acc<DT> &s) {
-      const double value = s.value() + (qq == 0 ? tx : 0.0);
-      if (qq == 0) v0 = value;
-      const bool last = (qq == cnt - 1);
-      if (last) vlast = value;
-      const int idx = (last && ends_mid) ? stop : start + qq;
-      if (!(qq == 0 && start == r0) && (unsigned)idx < (unsigned)m) y[idx] = (y_t)value;
-    };
 #pragma unroll
     for (int i = 0; i < W; ++i) {
       if ((hb >> i) & 1u) {
-        if (rank > 0) emit(rank - 1, cur);
+        if (rank > 0) {
+          double pv = cur.value();
+          if (rank == 1) pv += tx;
+          part[rank - 1] = pv;
+        }
         ++rank;
         cur.zero();
       }
       cur.add(v[i]);
     }
-    if (lane == kWave - 1) emit(cnt - 1, cur);
+    if (lane == kWave - 1) {
+      double pv = cur.value();
+      if (cnt == 1) pv += tx;
+      part[cnt - 1] = pv;
+    }
+    __builtin_amdgcn_wave_barrier();
 
-    // rank 0 is emitted by the first lane whose inclusive head count reaches
-    // 2, or by the last lane when the tile has a single segment
-    const uint64_t bal2 = __ballot(incl >= 2);
-    const int l0 = bal2 ? (__ffsll((unsigned long long)bal2) - 1) : (kWave - 1);
-    const double v0u = __shfl(v0, l0, kWave);
-    if (start == r0) sync_v = v0u;
-    const double vlast_u = __shfl(vlast, kWave - 1, kWave);
-    transmitter = ends_mid ? vlast_u : 0.0;
+    // ---- coalesced store of the compact partials to y[start + q]; the
+    // bunch's first segment goes to the synchronizer; a tile that ends inside
+    // row `stop` writes its last partial at y[stop] and transmits it
+    for (int q = lane; q < cnt; q += kWave) {
+      const double pv = part[q];
+      const bool last = (q == cnt - 1);
+      const int idx = (last && ends_mid) ? stop : start + q;
+      if (!(q == 0 && start == r0) && (unsigned)idx < (unsigned)m) y_store((y_t)pv, &y[idx]);
+    }
+    const double p0 = part[0];
+    const double plast = part[cnt - 1];
+    if (start == r0) sync_v = p0;
+    transmitter = ends_mid ? plast : 0.0;
+    __builtin_amdgcn_wave_barrier();
 
-    // ---- dirty tile: label it for the re-arrangement
+    // ---- dirty tile: label it for the re-arrangement, in this bunch's own
+    // speculator slots (no global counter)
     if (dirty && lane == 0) {
-      const int pos = atomicAdd(&a.counters[0], 1);
-      if (pos < a.n_tiles) a.speculator[pos] = make_int4(start, stop, (int)tile, 0);
+      const int slot = __popc(dirty_bits & ((1u << t) - 1u));
+      a.speculator[tb * S + slot] = make_int4(start, stop, (int)tile, 0);
     }
   }
   if (lane == 0) {
     a.sync_idx[tb] = r0;
     a.sync_val[tb] = sync_v;
+    a.dirty_mask[tb] = dirty_bits;
   }
 }
 
@@ -441,30 +578,30 @@ struct FixupArgs {
   int64_t SWT;
   int64_t n_bunches;
   int64_t n_tiles;
-  int *counters;
+  int32_t S;
+  const uint32_t *dirty_mask;
   const int4 *speculator;
   const int32_t *sync_idx;
   const double *sync_val;
 };
 
 template <typename YT>
-__global__ __launch_bounds__(256) void sss_fixup(FixupArgs a) {
+__global__ __launch_bounds__(1024) void sss_fixup(FixupArgs a) {
   extern __shared__ unsigned char lds_raw[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.WT;
   const int32_t *__restrict__ rp = a.row_ptr;
   YT *y = static_cast<YT *>(a.y);
-  const int n_dirty = (int)min<int64_t>(
-      __hip_atomic_load(&a.counters[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.n_tiles);
-
   // (1) re-arrange each dirty tile: its partials 1.. sit at y[start+1..]; the
   // k-th non-empty row strictly between start and stop receives partial k,
   // the empty rows there receive 0.  Only rows strictly inside the tile.
+  // One wavefront per thread-bunch, over that bunch's dirty tiles.
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
-  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t ent = wave; ent < n_dirty; ent += n_waves) {
-    const int4 s = a.speculator[ent];
+  const uint32_t dm = wave < a.n_bunches ? a.dirty_mask[wave] : 0u;
+  const int n_dirty = __popc(dm);
+  for (int ent = 0; ent < n_dirty; ++ent) {
+    const int4 s = a.speculator[wave * a.S + ent];
     const int start = s.x, stop = s.y;
     const int n_slots = min(stop - start - 1, a.WT - 1);
     for (int i = lane; i < n_slots; i += kWave) slots[i] = y[start + 1 + i];
@@ -485,36 +622,64 @@ __global__ __launch_bounds__(256) void sss_fixup(FixupArgs a) {
   }
 
   // (2) synchronizer carries: for each run of bunches whose first row is the
-  // same row r, add their first-segment sums to y[r] in bunch order, in
-  // double.  y[r] holds the part of r computed before the run, unless row r
-  // begins exactly where the run's first bunch begins.
+  // same row r, add their first-segment sums to y[r], in double.  y[r] holds
+  // the part of r computed before the run, unless row r begins exactly where
+  // the run's first bunch begins.  Runs of up to kShortRun bunches are summed
+  // by the run's first thread in bunch order; longer runs (rows longer than
+  // kShortRun bunches) by the whole wavefront: coalesced loads, per-lane
+  // partial sums, then a fixed-shape tree over the lanes, so the rounding
+  // does not depend on timing.
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n_thr = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t tb = tid; tb < a.n_bunches; tb += n_thr) {
-    const int idx = a.sync_idx[tb];
-    if (tb > 0 && a.sync_idx[tb - 1] == idx) continue;
-    double s = 0.0;
-    for (int64_t t2 = tb; t2 < a.n_bunches && a.sync_idx[t2] == idx; ++t2) s += a.sync_val[t2];
-    const bool fresh = (int64_t)rp[idx] == tb * a.SWT;
-    y[idx] = fresh ? (YT)s : (YT)((double)y[idx] + s);
+  const int64_t nb = a.n_bunches;
+  for (int64_t base = tid - lane; base < nb; base += n_thr) {
+    const int64_t tb = base + lane;
+    const bool valid = tb < nb;
+    const int idx = valid ? a.sync_idx[tb] : -1;
+    const bool head = valid && (tb == 0 || a.sync_idx[tb - 1] != idx);
+    const bool is_long = head && (tb + kShortRun < nb) && (a.sync_idx[tb + kShortRun] == idx);
+    if (head && !is_long) {
+      // sync_idx is non-decreasing: the run is a prefix of the next kShortRun
+      int idn[kShortRun];
+      double vv[kShortRun];
+#pragma unroll
+      for (int j = 0; j < kShortRun; ++j) {
+        const bool in = tb + j < nb;
+        idn[j] = in ? a.sync_idx[tb + j] : -1;
+        vv[j] = in ? a.sync_val[tb + j] : 0.0;
+      }
+      double sum = 0.0;
+#pragma unroll
+      for (int j = 0; j < kShortRun; ++j)
+        if (idn[j] == idx) sum += vv[j];
+      const bool fresh = (int64_t)rp[idx] == tb * a.SWT;
+      y[idx] = fresh ? (YT)sum : (YT)((double)y[idx] + sum);
+    }
+    uint64_t longs = __ballot(is_long);
+    while (longs) {
+      const int l = __ffsll((unsigned long long)longs) - 1;
+      longs &= longs - 1;
+      const int64_t t0 = __shfl(tb, l, kWave);
+      const int ridx = __shfl(idx, l, kWave);
+      double acc = 0.0;
+      for (int64_t off = 0;; off += kWave) {
+        const int64_t j = t0 + off + lane;
+        const bool in = j < nb && a.sync_idx[j] == ridx;
+        if (in) acc += a.sync_val[j];
+        if (__ballot(in) != ~0ull) break;
+      }
+      const double total = wave_sum_tree(acc);
+      if (lane == l) {
+        const bool fresh = (int64_t)rp[ridx] == t0 * a.SWT;
+        y[ridx] = fresh ? (YT)total : (YT)((double)y[ridx] + total);
+      }
+    }
   }
 
   // (3) rows before the first tile's start row are empty and covered by no tile
   const int r_first = a.n_bunches > 0 ? a.sync_idx[0] : a.m;
   for (int64_t r = tid; r < r_first; r += n_thr) y[r] = (YT)0;
 
-  // the last block to finish resets the dirty counter for the next call
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(&a.counters[1], 1);
-    if (prev == (int)gridDim.x - 1) {
-      a.counters[2] = n_dirty;
-      a.counters[0] = 0;
-      a.counters[1] = 0;
-      __threadfence();
-    }
-  }
 }
 
 template <typename YT>
@@ -539,6 +704,11 @@ __global__ void sss_validate_kernel(const int32_t *rp, const int32_t *col, int64
 int default_W(int dt) { return dt == SSS_F64 ? 8 : 16; }
 int default_S(int dt) { return dt == SSS_F64 ? 5 : 2; }
 constexpr int kDefaultB = 2;
+#ifndef SSS_FIXUP_THREADS
+#define SSS_FIXUP_THREADS 256
+#endif
+constexpr int kFixupThreads = SSS_FIXUP_THREADS;
+constexpr size_t kFixupLdsBytes = 64 * 1024;  // LDS of one fixup workgroup
 constexpr int kMaxS = 16;
 
 bool dtype_ok(int dt) { return dt == SSS_F64 || dt == SSS_F32 || dt == SSS_BF16; }
@@ -578,7 +748,7 @@ struct sss_plan_s {
   int debug = 0;
   int64_t n_tiles = 0, n_bunches = 0;
   void *aux = nullptr;
-  int *counters = nullptr;
+  uint32_t *dirty_mask = nullptr;
   int4 *speculator = nullptr;
   int32_t *sync_idx = nullptr;
   double *sync_val = nullptr;
@@ -598,8 +768,8 @@ int plan_alloc(sss_plan p) {
   p->n_bunches = p->nnz > 0 ? (p->nnz + SWT - 1) / SWT : 0;
   const int64_t nt = p->n_tiles, nb = p->n_bunches;
   size_t off = 0;
-  const size_t o_cnt = off; off = align256(off + 16);
-  const size_t o_spec = off; off = align256(off + sizeof(int4) * (size_t)(nt + 1));
+  const size_t o_dmask = off; off = align256(off + sizeof(uint32_t) * (size_t)(nb + 1));
+  const size_t o_spec = off; off = align256(off + sizeof(int4) * (size_t)(nb * p->S + 1));
   const size_t o_sidx = off; off = align256(off + sizeof(int32_t) * (size_t)(nb + 1));
   const size_t o_sval = off; off = align256(off + sizeof(double) * (size_t)(nb + 1));
   size_t o_ds = 0, o_dd = 0, o_dh = 0;
@@ -611,7 +781,7 @@ int plan_alloc(sss_plan p) {
   SSS_HIP(hipMalloc(&p->aux, off));
   SSS_HIP(hipMemset(p->aux, 0, off));
   char *base = static_cast<char *>(p->aux);
-  p->counters = reinterpret_cast<int *>(base + o_cnt);
+  p->dirty_mask = reinterpret_cast<uint32_t *>(base + o_dmask);
   p->speculator = reinterpret_cast<int4 *>(base + o_spec);
   p->sync_idx = reinterpret_cast<int32_t *>(base + o_sidx);
   p->sync_val = reinterpret_cast<double *>(base + o_sval);
@@ -626,10 +796,23 @@ int plan_alloc(sss_plan p) {
 
 bool misaligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
 
-int launch(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x, void *y,
-           hipStream_t stream) {
+int check_call(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x, void *y) {
   if (p->m == 0) return SSS_OK;
   if (!row_ptr || !y) return SSS_ERR_INVALID_VALUE;
+  if (p->nnz > 0) {
+    if (!col || !val || !x) return SSS_ERR_INVALID_VALUE;
+    if (misaligned(col) || misaligned(val)) return SSS_ERR_INVALID_VALUE;
+  }
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
+  return SSS_OK;
+}
+
+// Stage 1: speculative execution.  (nnz = 0: y is zeroed here.)
+int launch_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x, void *y,
+                  hipStream_t stream) {
+  if (p->m == 0) return SSS_OK;
   if (p->nnz == 0) {
     const int blocks = (int)std::min<int64_t>((p->m + 255) / 256, 4096);
     if (p->dt == SSS_F64)
@@ -639,38 +822,51 @@ int launch(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *v
     SSS_HIP(hipGetLastError());
     return SSS_OK;
   }
-  if (!col || !val || !x) return SSS_ERR_INVALID_VALUE;
-  if (misaligned(col) || misaligned(val)) return SSS_ERR_INVALID_VALUE;
-  int dev = -1;
-  SSS_HIP(hipGetDevice(&dev));
-  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
-
   Stage1Fn k1 = pick_stage1(p->dt, p->W, p->debug != 0);
   if (!k1) return SSS_ERR_UNSUPPORTED;
   const int WT = p->W * kWave;
   Stage1Args a1;
   a1.row_ptr = row_ptr; a1.col = col; a1.val = val; a1.x = x; a1.y = y;
   a1.m = (int32_t)p->m; a1.nnz = (int32_t)p->nnz; a1.S = p->S; a1.n_bunches = p->n_bunches; a1.n_tiles = p->n_tiles;
-  a1.counters = p->counters; a1.speculator = p->speculator; a1.sync_idx = p->sync_idx; a1.sync_val = p->sync_val;
+  a1.dirty_mask = p->dirty_mask; a1.speculator = p->speculator; a1.sync_idx = p->sync_idx; a1.sync_val = p->sync_val;
   a1.dbg_start = p->dbg_start; a1.dbg_dirty = p->dbg_dirty; a1.dbg_heads = p->dbg_heads;
   const int64_t blocks1 = (p->n_bunches + p->B - 1) / p->B;
-  const size_t lds1 = (size_t)p->B * p->S * (WT / 32) * sizeof(uint32_t);
+  const size_t lds1 = (size_t)p->B * stage1_lds_words(p->W, p->S) * sizeof(uint32_t);
   hipLaunchKernelGGL(k1, dim3((unsigned)blocks1), dim3(p->B * kWave), lds1, stream, a1);
   SSS_HIP(hipGetLastError());
+  return SSS_OK;
+}
 
+// Stage 2: checking prediction (synchronizer carries, dirty-tile
+// re-arrangement, leading empty rows).
+int launch_stage2(sss_plan p, const int32_t *row_ptr, void *y, hipStream_t stream) {
+  if (p->m == 0 || p->nnz == 0) return SSS_OK;
+  const int WT = p->W * kWave;
   FixupArgs a2;
   a2.row_ptr = row_ptr; a2.y = y; a2.m = (int32_t)p->m; a2.nnz = (int32_t)p->nnz; a2.WT = WT;
-  a2.SWT = (int64_t)p->S * WT; a2.n_bunches = p->n_bunches; a2.n_tiles = p->n_tiles; a2.counters = p->counters;
+  a2.SWT = (int64_t)p->S * WT; a2.n_bunches = p->n_bunches; a2.n_tiles = p->n_tiles; a2.S = p->S;
+  a2.dirty_mask = p->dirty_mask;
   a2.speculator = p->speculator; a2.sync_idx = p->sync_idx; a2.sync_val = p->sync_val;
-  int64_t blocks2 = std::max<int64_t>((p->n_tiles + 3) / 4, (p->n_bunches + 255) / 256);
-  blocks2 = std::max<int64_t>(1, std::min<int64_t>(blocks2, 2048));
-  const size_t lds2 = 4 * (size_t)WT * y_size(p->dt);
+  // one wavefront per thread-bunch (its dirty tiles), one thread per bunch
+  // (its carry run); the grid covers every bunch
+  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kFixupThreads / kWave, kFixupLdsBytes / ((size_t)WT * y_size(p->dt))));
+  const int64_t blocks2 = std::max<int64_t>(1, (p->n_bunches + wpb - 1) / wpb);
+  const size_t lds2 = (size_t)wpb * WT * y_size(p->dt);
   if (p->dt == SSS_F64)
-    hipLaunchKernelGGL(sss_fixup<double>, dim3((unsigned)blocks2), dim3(256), lds2, stream, a2);
+    hipLaunchKernelGGL(sss_fixup<double>, dim3((unsigned)blocks2), dim3(wpb * kWave), lds2, stream, a2);
   else
-    hipLaunchKernelGGL(sss_fixup<float>, dim3((unsigned)blocks2), dim3(256), lds2, stream, a2);
+    hipLaunchKernelGGL(sss_fixup<float>, dim3((unsigned)blocks2), dim3(wpb * kWave), lds2, stream, a2);
   SSS_HIP(hipGetLastError());
   return SSS_OK;
+}
+
+int launch(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x, void *y,
+           hipStream_t stream) {
+  int rc = check_call(p, row_ptr, col, val, x, y);
+  if (rc != SSS_OK || p->m == 0) return rc;
+  rc = launch_stage1(p, row_ptr, col, val, x, y, stream);
+  if (rc != SSS_OK) return rc;
+  return launch_stage2(p, row_ptr, y, stream);
 }
 
 std::mutex g_cache_mu;
@@ -715,6 +911,21 @@ int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col,
                          void *y, void *stream) {
   if (!p) return SSS_ERR_INVALID_VALUE;
   return launch(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sss_csr_spmv_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x,
+                        void *y, void *stream) {
+  if (!p) return SSS_ERR_INVALID_VALUE;
+  const int rc = check_call(p, row_ptr, col, val, x, y);
+  if (rc != SSS_OK || p->m == 0) return rc;
+  return launch_stage1(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *stream) {
+  if (!p) return SSS_ERR_INVALID_VALUE;
+  if (p->m == 0) return SSS_OK;
+  if (!row_ptr || !y) return SSS_ERR_INVALID_VALUE;
+  return launch_stage2(p, row_ptr, y, static_cast<hipStream_t>(stream));
 }
 
 int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, const double *val,
@@ -798,12 +1009,20 @@ int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes) {
   if (!host_buf || bytes < need) return SSS_ERR_INVALID_VALUE;
   SSS_HIP(hipDeviceSynchronize());
   std::memset(host_buf, 0, need);
-  int cnt[4] = {0, 0, 0, 0};
-  SSS_HIP(hipMemcpy(cnt, p->counters, sizeof(cnt), hipMemcpyDeviceToHost));
   const int64_t nt = p->n_tiles, nb = p->n_bunches;
   const int64_t wpt = (int64_t)p->W * kWave / 32;
+  // the per-bunch speculator segments, packed into one list in bunch order
+  std::vector<uint32_t> dmask((size_t)nb);
+  std::vector<int4> spec((size_t)(nb * p->S));
+  if (nb > 0) {
+    SSS_HIP(hipMemcpy(dmask.data(), p->dirty_mask, nb * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    SSS_HIP(hipMemcpy(spec.data(), p->speculator, nb * p->S * sizeof(int4), hipMemcpyDeviceToHost));
+  }
+  std::vector<int4> packed;
+  for (int64_t b = 0; b < nb; ++b)
+    for (int i = 0; i < __builtin_popcount(dmask[(size_t)b]); ++i) packed.push_back(spec[(size_t)(b * p->S + i)]);
   int64_t *hdr = static_cast<int64_t *>(host_buf);
-  hdr[0] = nt; hdr[1] = nb; hdr[2] = cnt[2]; hdr[3] = wpt;
+  hdr[0] = nt; hdr[1] = nb; hdr[2] = (int64_t)packed.size(); hdr[3] = wpt;
   char *cur = reinterpret_cast<char *>(hdr + 4);
   if (p->debug && nt > 0) {
     SSS_HIP(hipMemcpy(cur, p->dbg_start, nt * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -812,7 +1031,7 @@ int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes) {
                       hipMemcpyDeviceToHost));
   }
   cur += nt * (2 * sizeof(int32_t) + wpt * sizeof(uint32_t));
-  if (cnt[2] > 0) SSS_HIP(hipMemcpy(cur, p->speculator, (size_t)cnt[2] * sizeof(int4), hipMemcpyDeviceToHost));
+  if (!packed.empty()) std::memcpy(cur, packed.data(), packed.size() * sizeof(int4));
   cur += nt * 4 * sizeof(int32_t);
   if (nb > 0) {
     SSS_HIP(hipMemcpy(cur, p->sync_idx, nb * sizeof(int32_t), hipMemcpyDeviceToHost));

@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsss.so")
+# SSS_LIBRARY selects another build of the same C ABI (for A/B timing)
+LIB_PATH = os.environ.get("SSS_LIBRARY", os.path.join(HERE, "libsss.so"))
 
 F64, F32, BF16 = 0, 1, 2
 MODE_SELECTOR, MODE_GRID, MODE_FIXED = 0, 1, 2
@@ -60,6 +61,8 @@ def lib():
                                                ctypes.POINTER(P)]
         L.sss_csr_spmv_execute.argtypes = [P, P, P, P, P, P, P]
         L.sss_csr_spmv.argtypes = [I64, I64, I64, P, P, P, P, P, P]
+        L.sss_csr_spmv_stage1.argtypes = [P, P, P, P, P, P, P]
+        L.sss_csr_spmv_stage2.argtypes = [P, P, P, P]
         L.sss_plan_destroy.argtypes = [P]
         L.sss_plan_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                     ctypes.POINTER(I64), ctypes.POINTER(I64)]
@@ -71,6 +74,7 @@ def lib():
         L.sss_last_hip_error.restype = ctypes.c_char_p
         L.sss_version.restype = ctypes.c_char_p
         for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_plan_destroy",
+                  "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump"):
             getattr(L, f).restype = I
         _lib = L
@@ -141,6 +145,15 @@ class Plan:
                                         _stream(stream))
         _check(rc, "sss_csr_spmv_execute")
         return y
+
+    def stage1(self, row_ptr, col, val, x, y, stream=None):
+        """Speculative execution only (sss_csr_spmv_stage1)."""
+        _check(lib().sss_csr_spmv_stage1(self._h, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
+                                         _stream(stream)), "sss_csr_spmv_stage1")
+
+    def stage2(self, row_ptr, y, stream=None):
+        """Checking prediction only (sss_csr_spmv_stage2)."""
+        _check(lib().sss_csr_spmv_stage2(self._h, _ptr(row_ptr), _ptr(y), _stream(stream)), "sss_csr_spmv_stage2")
 
     def debug_dump(self) -> dict:
         L = lib()

@@ -215,3 +215,19 @@ def _config2_ref():
         _C2["ref"] = oracle.spmv(A.row_ptr, A.col, A.val, x)
         _C2["scale"] = oracle.abs_spmv(A.row_ptr, A.col, A.val, x)
     return _C2["ref"], _C2["scale"]
+
+
+@pytest.mark.parametrize("k", [15, 16, 17, 63, 64, 65, 130])
+@pytest.mark.parametrize("delta", [-1, 0, 1])
+def test_synchronizer_runs(torch_cuda, k, delta):
+    """Rows spanning k thread-bunches: short and long carry runs, a long row
+    first and last, and two long rows back to back."""
+    W, S = 4, 1
+    swt = S * W * 64
+    L = k * swt + delta
+    lengths = [L, 3, 0, L + 7, L, 5, 0, 0, 2, L]
+    A, x = csr_from_lengths(lengths, L + 8, seed=k * 3 + delta)
+    y, _ = run_plan(torch_cuda, A, x, W=W, S=S)
+    assert_exact(y, oracle.spmv(A.row_ptr, A.col, A.val, x))
+    y2, _ = run_plan(torch_cuda, A, x, W=8, S=2)
+    assert_exact(y2, oracle.spmv(A.row_ptr, A.col, A.val, x))
