@@ -42,6 +42,22 @@ def paper_bytes(m: int, nnz: int, val_size: int) -> int:
     return (m + 1 + nnz) * 4 + (2 * nnz + m) * val_size
 
 
+def measured_traffic(W: int, S: int, B: int):
+    """HBM-side bytes per stage-1 launch from the committed counter record,
+    or None when the kernel source or launch shape differs from the one the
+    counters were taken on."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(here, "profiles", "traffic.json")))["sss_stage1"]
+        src = open(os.path.join(here, "paper_1504_06474_amd", "csrc", "sss_spmv.hip"), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"] or (W, S, B) != (rec["W"], rec["S"], rec["B"]):
+        return None
+    return int(rec["fetch_kib_raw"] * rec["fetch_factor"] * 1024 + rec["write_kib_raw"] * rec["write_factor"] * 1024)
+
+
 def cpu_baseline(A, x, seconds: float) -> dict:
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
@@ -57,6 +73,90 @@ def cpu_baseline(A, x, seconds: float) -> dict:
     return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"the full benchmark matrix ({A.nnz} nnz), {reps} repetitions of the Dot2 FP64 "
                       f"row loop with OpenMP over rows, {el:.1f} s"}
+
+
+def time_steps(torch, plan, copies, steps: int, warmup: int) -> float:
+    """Average ms per y = A x over `steps` launches, rotating the copies."""
+    for k in range(warmup):
+        rp, col, v, xx, y = copies[k % len(copies)]
+        plan.execute(rp, col, v, xx, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        rp, col, v, xx, y = copies[k % len(copies)]
+        plan.execute(rp, col, v, xx, y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def error_stats(y, ref, scale) -> dict:
+    """Per-row error scaled by (|A||x|)_i, and plain relative error over rows
+    that do not cancel (|y_i| >= 1e-3 (|A||x|)_i)."""
+    y = np.asarray(y, dtype=np.float64)
+    nz = scale > 0
+    e = np.abs(y - ref)[nz] / scale[nz]
+    keep = np.abs(ref) >= 1e-3 * scale
+    rel = np.abs(y - ref)[keep] / np.abs(ref)[keep]
+    return {"max_scaled": float(e.max()) if e.size else 0.0, "median_scaled": float(np.median(e)) if e.size else 0.0,
+            "max_rel": float(rel.max()) if rel.size else 0.0, "median_rel": float(np.median(rel)) if rel.size else 0.0}
+
+
+def precision_block(torch, sss, steps: int, warmup: int) -> dict:
+    """The 4M-row Zipf-1.8 matrix stored FP64 / FP32 / BF16: time per y = A x
+    and the error against the FP64 oracle, for uniform and lognormal values."""
+    import csrgen
+    import oracle
+    log("[bench] precision: generating the 4M-row Zipf 1.8 matrix (seed 5)")
+    A, x = csrgen.config5()
+    out = {"workload": "zipf18_4M", "m": A.m, "nnz": A.nnz}
+    sizes = {"f64": (8, 8), "f32": (4, 4), "bf16": (2, 4)}
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+    for values in ("uniform", "lognormal"):
+        Av = A if values == "uniform" else csrgen.with_values(A, "lognormal", 55)
+        ref64 = oracle.spmv(Av.row_ptr, Av.col, Av.val, x)
+        sc64 = oracle.abs_spmv(Av.row_ptr, Av.col, Av.val, x)
+        for kind in ("f64", "f32", "bf16"):
+            vs, xs, ve, xe = csrgen.quantize(Av, x, kind)
+            rp = torch.from_numpy(Av.row_ptr).cuda()
+            col = torch.from_numpy(Av.col).cuda()
+            if kind == "bf16":
+                v = torch.from_numpy(vs.view(np.int16)).cuda().view(torch.bfloat16)
+            else:
+                v = torch.from_numpy(np.ascontiguousarray(vs)).cuda()
+            xx = torch.from_numpy(np.ascontiguousarray(xs)).cuda()
+            ydt = torch.float64 if kind == "f64" else torch.float32
+            plan = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind])
+            info = plan.info()
+            rec = out.setdefault(kind, {"W": info["W"], "S": info["S"]})
+            if values == "uniform":
+                copies = [(rp, col, v, xx, torch.empty(A.m, dtype=ydt, device="cuda"))]
+                for _ in range(2):
+                    copies.append((rp.clone(), col.clone(), v.clone(), xx.clone(),
+                                   torch.empty(A.m, dtype=ydt, device="cuda")))
+                ms = time_steps(torch, plan, copies, steps, warmup)
+                vb, xb = sizes[kind]
+                rec.update({"us": round(ms * 1e3, 2), "GFLOPs": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
+                            "alg_GBps": round(alg_bytes(A.m, A.n, A.nnz, vb, xb) / (ms * 1e-3) / 1e9, 1)})
+                y = copies[0][4]
+                del copies
+            else:
+                y = torch.empty(A.m, dtype=ydt, device="cuda")
+                plan.execute(rp, col, v, xx, y)
+            torch.cuda.synchronize()
+            yh = y.double().cpu().numpy()
+            rec.setdefault("err_vs_f64_oracle", {})[values] = error_stats(yh, ref64, sc64)
+            if kind != "f64":
+                refq = oracle.spmv(Av.row_ptr, Av.col, ve, xe)
+                scq = oracle.abs_spmv(Av.row_ptr, Av.col, ve, xe)
+                rec.setdefault("err_arith_only", {})[values] = error_stats(yh, refq, scq)
+            del rp, col, v, xx, y
+            plan.close()
+            log(f"[bench] precision {values} {kind}: {rec.get('us')} us")
+    for kind in ("f32", "bf16"):
+        out[kind]["speedup_vs_f64"] = round(out["f64"]["us"] / out[kind]["us"], 3)
+    return out
 
 
 def run_copy_calibration(steps: int):
@@ -90,6 +190,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["spmv", "copy"], default="spmv")
+    ap.add_argument("--skip-precision", action="store_true", help="skip the FP32/BF16 comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -203,7 +304,8 @@ def main():
         "config": {"workload": "powerlaw_1M_zipf2_f64", "m": m, "n": n, "nnz": nnz, "W": info["W"],
                    "S": info["S"], "B": info["B"], "T": 64, "copies_rotated": len(copies)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": measured_traffic(info["W"], info["S"], info["B"]),
                      "kernel": "sss_stage1<f64,W>", "alg_bytes_per_launch": B,
                      "avg_launch_us": round(s1_ms * 1e3, 2)},
         "extras": {
@@ -218,6 +320,9 @@ def main():
             "sampled_max_rel_err": max_rel,
         },
     }
+    if not args.skip_precision:
+        del copies
+        out["extras"]["precision"] = precision_block(torch, sss, min(args.steps, 50), min(args.warmup, 5))
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, x, args.cpu_seconds)

@@ -49,6 +49,8 @@ __all__ = [
     "round_to_f32",
     "round_to_bf16",
     "bf16_bits",
+    "with_values",
+    "quantize",
 ]
 
 
@@ -416,3 +418,38 @@ def selector_matrix(i: int, seed0: int = 10000, m_lo: float = 1e4, m_hi: float =
     if cls == "weblike":
         return weblike_csr(max(100, int(target)), seed, values=values)
     return dense_rows_csr(max(1000, int(target) // 2), seed, values=values)
+
+
+def with_values(A: CSR, kind: str, seed: int) -> CSR:
+    """Same structure, new seeded values ("uniform", "int" or "lognormal")."""
+    rng = rng_for(seed)
+    if kind == "uniform":
+        val = uniform_values(rng, A.nnz)
+    elif kind == "int":
+        val = integer_values(rng, A.nnz)
+    elif kind == "lognormal":
+        val = lognormal_values(rng, A.nnz)
+    else:
+        raise ValueError(kind)
+    return CSR(A.m, A.n, A.row_ptr, A.col, val, A.name + "_" + kind)
+
+
+def quantize(A: CSR, x: np.ndarray, kind: str):
+    """Storage copies for the reduced-precision path and their exact values.
+
+    kind "f64": unchanged.  "f32": val and x rounded to binary32.  "bf16": val
+    rounded to bfloat16 (via binary32, nearest-even), x to binary32.
+    Returns (val_store, x_store, val_exact, x_exact): the arrays to hand to the
+    GPU (bf16 as uint16 bit patterns) and their values as float64.
+    """
+    if kind == "f64":
+        return A.val, x, A.val, x
+    x32 = round_to_f32(x)
+    if kind == "f32":
+        v32 = round_to_f32(A.val)
+        return v32, x32, v32.astype(np.float64), x32.astype(np.float64)
+    if kind == "bf16":
+        bits = bf16_bits(round_to_f32(A.val))
+        exact = (bits.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+        return bits, x32, exact, x32.astype(np.float64)
+    raise ValueError(kind)

@@ -59,3 +59,33 @@ def csr_from_lengths(lengths, n, seed=0, int_valued=True):
     A = csrgen.lengths_to_csr(rng, np.asarray(lengths, dtype=np.int64), n, "int" if int_valued else "uniform")
     x = csrgen.integer_values(rng, n) if int_valued else csrgen.uniform_values(rng, n)
     return A, x
+
+
+def to_dev_precision(A, x, kind):
+    """Device tensors for dtype kind ("f64", "f32", "bf16") and the exact
+    float64 values of what was stored (for the oracle)."""
+    import torch
+    import csrgen
+    vs, xs, ve, xe = csrgen.quantize(A, x, kind)
+    dev = "cuda"
+    rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int32)).to(dev)
+    col = torch.from_numpy(np.ascontiguousarray(A.col, dtype=np.int32)).to(dev)
+    if kind == "bf16":
+        v = torch.from_numpy(vs.view(np.int16)).to(dev).view(torch.bfloat16)
+    else:
+        v = torch.from_numpy(np.ascontiguousarray(vs)).to(dev)
+    xx = torch.from_numpy(np.ascontiguousarray(xs)).to(dev)
+    return rp, col, v, xx, ve, xe
+
+
+def assert_f32_path_bound(y, y_ref, scale):
+    """Reduced-precision path: float products (rounding u = 2^-24 each),
+    compensated sums (O(u^2)), one final rounding of y to float: the error
+    against the oracle on the stored values is at most 2u (|A||x|)_i."""
+    y = np.asarray(y, dtype=np.float64)
+    bound = (2 * U32) * (1 + 1e-6) * scale
+    bad = np.abs(y - y_ref) > bound
+    if bad.any():
+        i = int(np.nonzero(bad)[0][0])
+        raise AssertionError(f"{int(bad.sum())} rows over the bound; row {i}: got {y[i]!r} want {y_ref[i]!r} "
+                             f"bound {bound[i]!r}")
