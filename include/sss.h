@@ -120,6 +120,39 @@ int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                  const int32_t *col, const double *val, const double *x, double *y,
                  void *stream);
 
+/* One matrix of a batch: device pointers (caller-owned, as for execute), its
+ * sizes, and optionally its own S (tiles per wavefront; 0 = the batch's). */
+typedef struct {
+  int64_t m, n, nnz;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const void *val;
+  const void *x;
+  void *y;
+  int S;
+  int reserved;
+} sss_csr_desc;
+
+/* A batch plan: y_i = A_i x_i for `count` matrices in one persistent launch
+ * per stage.  The thread-bunches of all matrices form one nnz-balanced index
+ * space (Section 3.1's decomposition applied to the concatenation); each
+ * wavefront finds its matrix with the same rightmost-match search the method
+ * uses for rows (Section 3.2).  All matrices share dtype and W (opts); each
+ * may set its own S.  The descriptors' pointers are bound to the plan: the
+ * plan must be recreated if a matrix or vector moves.  Different matrices
+ * must not share y storage.  Allocates (the descriptors, prefix arrays and
+ * every matrix's synchronizer/speculator) and synchronises. */
+int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, const sss_plan_opts *opts,
+                          void *stream, sss_plan *out);
+
+/* Run a batch plan on `stream`: two launches (stage 1, stage 2), no
+ * allocation, no host synchronisation. */
+int sss_batch_execute(sss_plan p, void *stream);
+
+/* The same two launches captured once into a HIP graph (on the first call,
+ * on a private stream) and replayed on `stream` by every call. */
+int sss_batch_graph_launch(sss_plan p, void *stream);
+
 /* Free a plan's device buffers (synchronises the device first). NULL is OK. */
 int sss_plan_destroy(sss_plan p);
 

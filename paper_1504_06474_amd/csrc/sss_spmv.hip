@@ -231,24 +231,25 @@ __device__ __forceinline__ float scalar_val(const uint16_t *v, int k) { return b
 
 // ---------------------------------------------------------------- search
 
-// Largest r in [0, m] with rp[r] <= b (rp non-decreasing, rp[0] = 0 <= b).
+// Largest r in [0, m] with rp[r] <= b (rp non-decreasing, rp[0] <= b).
 // Wave-parallel 64-ary search: each round the 64 lanes probe 64 evenly spaced
 // points of (lo, hi]; the predicate rp[p] <= b holds for a prefix of lanes, so
 // its ballot's popcount picks the sub-interval.
-__device__ __forceinline__ int wave_rightmost(const int32_t *__restrict__ rp, int m, int b, int lane) {
-  int lo = 0, hi = m;
+template <typename T, typename I>
+__device__ __forceinline__ I wave_rightmost(const T *__restrict__ rp, I m, T b, int lane) {
+  I lo = 0, hi = m;
   while (hi - lo >= kWave) {
-    const int64_t span = hi - lo;
-    const int p = lo + (int)(((int64_t)(lane + 1) * span) / kWave);
+    const int64_t span = (int64_t)(hi - lo);
+    const I p = lo + (I)(((int64_t)(lane + 1) * span) / kWave);
     const uint64_t bal = __ballot(rp[p] <= b);
     const int c = __popcll(bal);
-    const int newlo = c > 0 ? lo + (int)(((int64_t)c * span) / kWave) : lo;
-    const int newhi = c < kWave ? lo + (int)(((int64_t)(c + 1) * span) / kWave) - 1 : hi;
+    const I newlo = c > 0 ? lo + (I)(((int64_t)c * span) / kWave) : lo;
+    const I newhi = c < kWave ? lo + (I)(((int64_t)(c + 1) * span) / kWave) - 1 : hi;
     lo = newlo;
     hi = newhi;
   }
-  const int p = lo + lane;
-  const bool pred = (p <= hi) && (rp[min(p, hi)] <= b);
+  const I p = lo + lane;
+  const bool pred = (p <= hi) && (rp[p <= hi ? p : hi] <= b);
   return lo + __popcll(__ballot(pred)) - 1;
 }
 
@@ -328,7 +329,9 @@ __device__ __forceinline__ double wave_sum_tree(double v) {
 
 // ---------------------------------------------------------------- stage 1
 
-struct Stage1Args {
+// One matrix as the kernels see it: the caller's arrays, sizes, and the
+// plan's auxiliary arrays for this matrix (already offset to it).
+struct MatCtx {
   const int32_t *row_ptr;
   const int32_t *col;
   const void *val;
@@ -337,6 +340,7 @@ struct Stage1Args {
   int32_t m;
   int32_t nnz;
   int32_t S;
+  int32_t W;
   int64_t n_bunches;
   int64_t n_tiles;
   uint32_t *dirty_mask;  // per bunch: bit t set when its tile t is dirty
@@ -373,11 +377,7 @@ __device__ __forceinline__ void load_tile(const int32_t *__restrict__ col, const
 }
 
 template <int DT, int W, bool DEBUG>
-__global__ __launch_bounds__(256)
-#if SSS_WAVES_PER_EU
-__attribute__((amdgpu_waves_per_eu(SSS_WAVES_PER_EU, 8)))
-#endif
-void sss_stage1(Stage1Args a) {
+__device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, uint32_t *lds_wave, const int lane) {
   using val_t = typename VT<DT>::val_t;
   using x_t = typename VT<DT>::x_t;
   using y_t = typename VT<DT>::y_t;
@@ -386,19 +386,13 @@ void sss_stage1(Stage1Args a) {
   constexpr int WPT = WT / 32;  // descriptor words per tile
   constexpr uint32_t LOW = (W >= 32) ? 0xffffffffu : ((1u << W) - 1u);
 
-  extern __shared__ uint32_t lds_words[];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
-  const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
-  if (tb >= a.n_bunches) return;
-
   const int32_t *__restrict__ rp = a.row_ptr;
   const int32_t *__restrict__ col = a.col;
   const val_t *__restrict__ val = static_cast<const val_t *>(a.val);
   const x_t *__restrict__ x = static_cast<const x_t *>(a.x);
   y_t *__restrict__ y = static_cast<y_t *>(a.y);
   const int m = a.m, nnz = a.nnz, S = a.S;
-  uint32_t *mask = lds_words + wid * stage1_lds_words(W, S);
+  uint32_t *mask = lds_wave;
   uint32_t *dflag = mask + S * WPT;
   double *part = reinterpret_cast<double *>(mask + S * WPT + 2);
 
@@ -567,43 +561,68 @@ void sss_stage1(Stage1Args a) {
   }
 }
 
-// ---------------------------------------------------------------- stage 2
 
-struct FixupArgs {
-  const int32_t *row_ptr;
-  void *y;
-  int32_t m;
-  int32_t nnz;
-  int32_t WT;
-  int64_t SWT;
-  int64_t n_bunches;
-  int64_t n_tiles;
-  int32_t S;
-  const uint32_t *dirty_mask;
-  const int4 *speculator;
-  const int32_t *sync_idx;
-  const double *sync_val;
-};
-
-template <typename YT>
-__global__ __launch_bounds__(1024) void sss_fixup(FixupArgs a) {
-  extern __shared__ unsigned char lds_raw[];
+template <int DT, int W, bool DEBUG>
+__global__ __launch_bounds__(256)
+#if SSS_WAVES_PER_EU
+__attribute__((amdgpu_waves_per_eu(SSS_WAVES_PER_EU, 8)))
+#endif
+void sss_stage1(MatCtx a) {
+  extern __shared__ uint32_t lds_words[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.WT;
+  const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
+  if (tb >= a.n_bunches) return;
+  stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane);
+}
+
+// Many matrices in one persistent launch: the thread-bunches of all matrices
+// form one nnz-balanced index space (bunch_base = prefix of the per-matrix
+// bunch counts); each wavefront strides over it and finds its matrix by the
+// same rightmost-match search the method uses for rows.
+struct BatchArgs {
+  const MatCtx *mats;
+  const int64_t *bunch_base;  // [count+1]
+  const int64_t *chunk_base;  // [count+1] prefix of ceil(n_bunches / 64)
+  int32_t count;
+  int32_t S_max;
+  int64_t total_bunches;
+  int64_t total_chunks;
+  int64_t total_waves;        // stage-2 work items: max(total_bunches, count)
+};
+
+template <int DT, int W>
+__global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
+  extern __shared__ uint32_t lds_words[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  uint32_t *lds_wave = lds_words + wid * stage1_lds_words(W, b.S_max);
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid; g < b.total_bunches; g += n_waves) {
+    const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane);
+    const MatCtx a = b.mats[i];
+    stage1_bunch<DT, W, false>(a, g - b.bunch_base[i], lds_wave, lane);
+  }
+}
+
+
+// ---------------------------------------------------------------- stage 2
+
+// (1) re-arrange the dirty tiles of thread-bunch tb: a dirty tile's partials
+// 1.. sit at y[start+1..]; the k-th non-empty row strictly between start and
+// stop receives partial k, the empty rows there receive 0.  Only rows strictly
+// inside the tile are touched.  The partials are gathered into LDS first.
+template <typename YT>
+__device__ __forceinline__ void fixup_dirty(const MatCtx &a, const int64_t tb, YT *slots, const int lane) {
   const int32_t *__restrict__ rp = a.row_ptr;
   YT *y = static_cast<YT *>(a.y);
-  // (1) re-arrange each dirty tile: its partials 1.. sit at y[start+1..]; the
-  // k-th non-empty row strictly between start and stop receives partial k,
-  // the empty rows there receive 0.  Only rows strictly inside the tile.
-  // One wavefront per thread-bunch, over that bunch's dirty tiles.
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
-  const uint32_t dm = wave < a.n_bunches ? a.dirty_mask[wave] : 0u;
+  const int WT = a.W * kWave;
+  const uint32_t dm = a.dirty_mask[tb];
   const int n_dirty = __popc(dm);
   for (int ent = 0; ent < n_dirty; ++ent) {
-    const int4 s = a.speculator[wave * a.S + ent];
+    const int4 s = a.speculator[tb * a.S + ent];
     const int start = s.x, stop = s.y;
-    const int n_slots = min(stop - start - 1, a.WT - 1);
+    const int n_slots = min(stop - start - 1, WT - 1);
     for (int i = lane; i < n_slots; i += kWave) slots[i] = y[start + 1 + i];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -620,66 +639,115 @@ __global__ __launch_bounds__(1024) void sss_fixup(FixupArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
   }
+}
 
-  // (2) synchronizer carries: for each run of bunches whose first row is the
-  // same row r, add their first-segment sums to y[r], in double.  y[r] holds
-  // the part of r computed before the run, unless row r begins exactly where
-  // the run's first bunch begins.  Runs of up to kShortRun bunches are summed
-  // by the run's first thread in bunch order; longer runs (rows longer than
-  // kShortRun bunches) by the whole wavefront: coalesced loads, per-lane
-  // partial sums, then a fixed-shape tree over the lanes, so the rounding
-  // does not depend on timing.
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n_thr = (int64_t)gridDim.x * blockDim.x;
+// (2) synchronizer carries for thread-bunches chunk0 .. chunk0+63 (one lane
+// each): for each run of bunches whose first row is the same row r, add their
+// first-segment sums to y[r], in double.  y[r] holds the part of r computed
+// before the run, unless row r begins exactly where the run's first bunch
+// begins.  Runs of up to kShortRun bunches are summed by the run's first lane
+// in bunch order; longer runs (rows longer than kShortRun bunches) by the
+// whole wavefront: coalesced loads, per-lane partial sums, then a fixed-shape
+// tree over the lanes, so the rounding does not depend on timing.
+template <typename YT>
+__device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chunk0, const int lane) {
+  const int32_t *__restrict__ rp = a.row_ptr;
+  YT *y = static_cast<YT *>(a.y);
+  const int64_t SWT = (int64_t)a.S * a.W * kWave;
   const int64_t nb = a.n_bunches;
-  for (int64_t base = tid - lane; base < nb; base += n_thr) {
-    const int64_t tb = base + lane;
-    const bool valid = tb < nb;
-    const int idx = valid ? a.sync_idx[tb] : -1;
-    const bool head = valid && (tb == 0 || a.sync_idx[tb - 1] != idx);
-    const bool is_long = head && (tb + kShortRun < nb) && (a.sync_idx[tb + kShortRun] == idx);
-    if (head && !is_long) {
-      // sync_idx is non-decreasing: the run is a prefix of the next kShortRun
-      int idn[kShortRun];
-      double vv[kShortRun];
+  const int64_t tb = chunk0 + lane;
+  const bool valid = tb < nb;
+  const int idx = valid ? a.sync_idx[tb] : -1;
+  const bool head = valid && (tb == 0 || a.sync_idx[tb - 1] != idx);
+  const bool is_long = head && (tb + kShortRun < nb) && (a.sync_idx[tb + kShortRun] == idx);
+  if (head && !is_long) {
+    // sync_idx is non-decreasing: the run is a prefix of the next kShortRun
+    int idn[kShortRun];
+    double vv[kShortRun];
 #pragma unroll
-      for (int j = 0; j < kShortRun; ++j) {
-        const bool in = tb + j < nb;
-        idn[j] = in ? a.sync_idx[tb + j] : -1;
-        vv[j] = in ? a.sync_val[tb + j] : 0.0;
-      }
-      double sum = 0.0;
-#pragma unroll
-      for (int j = 0; j < kShortRun; ++j)
-        if (idn[j] == idx) sum += vv[j];
-      const bool fresh = (int64_t)rp[idx] == tb * a.SWT;
-      y[idx] = fresh ? (YT)sum : (YT)((double)y[idx] + sum);
+    for (int j = 0; j < kShortRun; ++j) {
+      const bool in = tb + j < nb;
+      idn[j] = in ? a.sync_idx[tb + j] : -1;
+      vv[j] = in ? a.sync_val[tb + j] : 0.0;
     }
-    uint64_t longs = __ballot(is_long);
-    while (longs) {
-      const int l = __ffsll((unsigned long long)longs) - 1;
-      longs &= longs - 1;
-      const int64_t t0 = __shfl(tb, l, kWave);
-      const int ridx = __shfl(idx, l, kWave);
-      double acc = 0.0;
-      for (int64_t off = 0;; off += kWave) {
-        const int64_t j = t0 + off + lane;
-        const bool in = j < nb && a.sync_idx[j] == ridx;
-        if (in) acc += a.sync_val[j];
-        if (__ballot(in) != ~0ull) break;
-      }
-      const double total = wave_sum_tree(acc);
-      if (lane == l) {
-        const bool fresh = (int64_t)rp[ridx] == t0 * a.SWT;
-        y[ridx] = fresh ? (YT)total : (YT)((double)y[ridx] + total);
-      }
+    double sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < kShortRun; ++j)
+      if (idn[j] == idx) sum += vv[j];
+    const bool fresh = (int64_t)rp[idx] == tb * SWT;
+    y[idx] = fresh ? (YT)sum : (YT)((double)y[idx] + sum);
+  }
+  uint64_t longs = __ballot(is_long);
+  while (longs) {
+    const int l = __ffsll((unsigned long long)longs) - 1;
+    longs &= longs - 1;
+    const int64_t t0 = __shfl(tb, l, kWave);
+    const int ridx = __shfl(idx, l, kWave);
+    double acc = 0.0;
+    for (int64_t off = 0;; off += kWave) {
+      const int64_t j = t0 + off + lane;
+      const bool in = j < nb && a.sync_idx[j] == ridx;
+      if (in) acc += a.sync_val[j];
+      if (__ballot(in) != ~0ull) break;
+    }
+    const double total = wave_sum_tree(acc);
+    if (lane == l) {
+      const bool fresh = (int64_t)rp[ridx] == t0 * SWT;
+      y[ridx] = fresh ? (YT)total : (YT)((double)y[ridx] + total);
     }
   }
+}
 
-  // (3) rows before the first tile's start row are empty and covered by no tile
-  const int r_first = a.n_bunches > 0 ? a.sync_idx[0] : a.m;
-  for (int64_t r = tid; r < r_first; r += n_thr) y[r] = (YT)0;
+// (3) rows before the first tile's start row are empty and covered by no
+// tile (all rows when nnz = 0): zero them, threads first..first+stride..
+template <typename YT>
+__device__ __forceinline__ void fixup_leading(const MatCtx &a, const int64_t first, const int64_t stride) {
+  YT *y = static_cast<YT *>(a.y);
+  const int64_t r_first = a.n_bunches > 0 ? a.sync_idx[0] : a.m;
+  for (int64_t r = first; r < r_first; r += stride) y[r] = (YT)0;
+}
 
+// Stage 2 of one matrix: wavefront w re-arranges bunch w's dirty tiles and
+// settles the carries of bunches 64w..64w+63; all threads share the leading
+// rows.  The three parts write disjoint rows.
+template <typename YT>
+__global__ __launch_bounds__(1024) void sss_fixup(MatCtx a) {
+  extern __shared__ unsigned char lds_raw[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
+  if (wave < a.n_bunches) fixup_dirty<YT>(a, wave, slots, lane);
+  if (wave * kWave < a.n_bunches) fixup_carries<YT>(a, wave * kWave, lane);
+  fixup_leading<YT>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// Stage 2 of a batch, persistent: work item w re-arranges global bunch w's
+// dirty tiles, settles carry chunk w (64 bunches of one matrix) and zeroes
+// matrix w's leading rows.
+template <typename YT>
+__global__ __launch_bounds__(1024) void sss_fixup_batch(BatchArgs b) {
+  extern __shared__ unsigned char lds_raw[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid; w < b.total_waves; w += n_waves) {
+    if (w < b.total_bunches) {
+      const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, w, lane);
+      const MatCtx a = b.mats[i];
+      YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
+      fixup_dirty<YT>(a, w - b.bunch_base[i], slots, lane);
+    }
+    if (w < b.total_chunks) {
+      const int i = (int)wave_rightmost(b.chunk_base, (int64_t)b.count, w, lane);
+      const MatCtx a = b.mats[i];
+      fixup_carries<YT>(a, (w - b.chunk_base[i]) * kWave, lane);
+    }
+    if (w < b.count) {
+      const MatCtx a = b.mats[w];
+      fixup_leading<YT>(a, lane, kWave);
+    }
+  }
 }
 
 template <typename YT>
@@ -714,7 +782,13 @@ constexpr int kMaxS = 16;
 bool dtype_ok(int dt) { return dt == SSS_F64 || dt == SSS_F32 || dt == SSS_BF16; }
 size_t y_size(int dt) { return dt == SSS_F64 ? 8 : 4; }
 
-using Stage1Fn = void (*)(Stage1Args);
+int fixup_waves_per_block(int W, int dt) {
+  return (int)std::max<size_t>(1, std::min<size_t>(kFixupThreads / kWave,
+                                                    kFixupLdsBytes / ((size_t)W * kWave * y_size(dt))));
+}
+
+using Stage1Fn = void (*)(MatCtx);
+using BatchFn = void (*)(BatchArgs);
 
 template <int DT, int W>
 Stage1Fn pick_dbg(bool dbg) { return dbg ? sss_stage1<DT, W, true> : sss_stage1<DT, W, false>; }
@@ -738,6 +812,25 @@ Stage1Fn pick_stage1(int dt, int W, bool dbg) {
   }
 }
 
+template <int DT>
+BatchFn pick_batch_w(int W) {
+  switch (W) {
+    case 4: return sss_stage1_batch<DT, 4>;
+    case 8: return sss_stage1_batch<DT, 8>;
+    case 16: return sss_stage1_batch<DT, 16>;
+    default: return nullptr;
+  }
+}
+
+BatchFn pick_stage1_batch(int dt, int W) {
+  switch (dt) {
+    case SSS_F64: return pick_batch_w<SSS_F64>(W);
+    case SSS_F32: return pick_batch_w<SSS_F32>(W);
+    case SSS_BF16: return pick_batch_w<SSS_BF16>(W);
+    default: return nullptr;
+  }
+}
+
 }  // namespace
 
 struct sss_plan_s {
@@ -755,6 +848,13 @@ struct sss_plan_s {
   int32_t *dbg_start = nullptr;
   int32_t *dbg_dirty = nullptr;
   uint32_t *dbg_heads = nullptr;
+  // batch plans only
+  bool batch = false;
+  BatchArgs bargs{};
+  int blocks1 = 0, blocks2 = 0, wpb2 = 1;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -824,10 +924,10 @@ int launch_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const 
   }
   Stage1Fn k1 = pick_stage1(p->dt, p->W, p->debug != 0);
   if (!k1) return SSS_ERR_UNSUPPORTED;
-  const int WT = p->W * kWave;
-  Stage1Args a1;
+  MatCtx a1{};
   a1.row_ptr = row_ptr; a1.col = col; a1.val = val; a1.x = x; a1.y = y;
-  a1.m = (int32_t)p->m; a1.nnz = (int32_t)p->nnz; a1.S = p->S; a1.n_bunches = p->n_bunches; a1.n_tiles = p->n_tiles;
+  a1.m = (int32_t)p->m; a1.nnz = (int32_t)p->nnz; a1.S = p->S; a1.W = p->W; a1.n_bunches = p->n_bunches;
+  a1.n_tiles = p->n_tiles;
   a1.dirty_mask = p->dirty_mask; a1.speculator = p->speculator; a1.sync_idx = p->sync_idx; a1.sync_val = p->sync_val;
   a1.dbg_start = p->dbg_start; a1.dbg_dirty = p->dbg_dirty; a1.dbg_heads = p->dbg_heads;
   const int64_t blocks1 = (p->n_bunches + p->B - 1) / p->B;
@@ -842,14 +942,13 @@ int launch_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const 
 int launch_stage2(sss_plan p, const int32_t *row_ptr, void *y, hipStream_t stream) {
   if (p->m == 0 || p->nnz == 0) return SSS_OK;
   const int WT = p->W * kWave;
-  FixupArgs a2;
-  a2.row_ptr = row_ptr; a2.y = y; a2.m = (int32_t)p->m; a2.nnz = (int32_t)p->nnz; a2.WT = WT;
-  a2.SWT = (int64_t)p->S * WT; a2.n_bunches = p->n_bunches; a2.n_tiles = p->n_tiles; a2.S = p->S;
-  a2.dirty_mask = p->dirty_mask;
+  MatCtx a2{};
+  a2.row_ptr = row_ptr; a2.y = y; a2.m = (int32_t)p->m; a2.nnz = (int32_t)p->nnz; a2.S = p->S; a2.W = p->W;
+  a2.n_bunches = p->n_bunches; a2.n_tiles = p->n_tiles; a2.dirty_mask = p->dirty_mask;
   a2.speculator = p->speculator; a2.sync_idx = p->sync_idx; a2.sync_val = p->sync_val;
   // one wavefront per thread-bunch (its dirty tiles), one thread per bunch
   // (its carry run); the grid covers every bunch
-  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(kFixupThreads / kWave, kFixupLdsBytes / ((size_t)WT * y_size(p->dt))));
+  const int wpb = fixup_waves_per_block(p->W, p->dt);
   const int64_t blocks2 = std::max<int64_t>(1, (p->n_bunches + wpb - 1) / wpb);
   const size_t lds2 = (size_t)wpb * WT * y_size(p->dt);
   if (p->dt == SSS_F64)
@@ -867,6 +966,28 @@ int launch(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *v
   rc = launch_stage1(p, row_ptr, col, val, x, y, stream);
   if (rc != SSS_OK) return rc;
   return launch_stage2(p, row_ptr, y, stream);
+}
+
+// Both stages of a batch plan: the persistent stage-1 launch, then the
+// persistent stage-2 launch.
+int launch_batch(sss_plan p, hipStream_t stream) {
+  if (p->bargs.total_waves == 0) return SSS_OK;
+  if (p->bargs.total_bunches > 0) {
+    BatchFn k1 = pick_stage1_batch(p->dt, p->W);
+    if (!k1) return SSS_ERR_UNSUPPORTED;
+    const size_t lds1 = (size_t)p->B * stage1_lds_words(p->W, p->bargs.S_max) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k1, dim3((unsigned)p->blocks1), dim3(p->B * kWave), lds1, stream, p->bargs);
+    SSS_HIP(hipGetLastError());
+  }
+  const size_t lds2 = (size_t)p->wpb2 * p->W * kWave * y_size(p->dt);
+  if (p->dt == SSS_F64)
+    hipLaunchKernelGGL(sss_fixup_batch<double>, dim3((unsigned)p->blocks2), dim3(p->wpb2 * kWave), lds2, stream,
+                       p->bargs);
+  else
+    hipLaunchKernelGGL(sss_fixup_batch<float>, dim3((unsigned)p->blocks2), dim3(p->wpb2 * kWave), lds2, stream,
+                       p->bargs);
+  SSS_HIP(hipGetLastError());
+  return SSS_OK;
 }
 
 std::mutex g_cache_mu;
@@ -909,20 +1030,20 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
 
 int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x,
                          void *y, void *stream) {
-  if (!p) return SSS_ERR_INVALID_VALUE;
+  if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
   return launch(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
 }
 
 int sss_csr_spmv_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x,
                         void *y, void *stream) {
-  if (!p) return SSS_ERR_INVALID_VALUE;
+  if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
   const int rc = check_call(p, row_ptr, col, val, x, y);
   if (rc != SSS_OK || p->m == 0) return rc;
   return launch_stage1(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
 }
 
 int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *stream) {
-  if (!p) return SSS_ERR_INVALID_VALUE;
+  if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
   if (p->m == 0) return SSS_OK;
   if (!row_ptr || !y) return SSS_ERR_INVALID_VALUE;
   return launch_stage2(p, row_ptr, y, static_cast<hipStream_t>(stream));
@@ -953,13 +1074,152 @@ int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, cons
 int sss_plan_destroy(sss_plan p) {
   if (!p) return SSS_OK;
   int rc = SSS_OK;
-  if (p->aux) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipFree(p->aux);
-    if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
-  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess && p->graph_exec) e = hipGraphExecDestroy(p->graph_exec);
+  if (e == hipSuccess && p->graph) e = hipGraphDestroy(p->graph);
+  if (e == hipSuccess && p->capture_stream) e = hipStreamDestroy(p->capture_stream);
+  if (e == hipSuccess && p->aux) e = hipFree(p->aux);
+  if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
   delete p;
   return rc;
+}
+
+int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, const sss_plan_opts *opts,
+                          void *stream, sss_plan *out) {
+  (void)stream;
+  if (!out || count < 0 || (count > 0 && !mats)) return SSS_ERR_INVALID_VALUE;
+  *out = nullptr;
+  if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
+  sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
+  if (opts) o = *opts;
+  if (o.mode != SSS_MODE_FIXED) return SSS_ERR_UNSUPPORTED;
+  const int W = o.W ? o.W : default_W(dt);
+  const int S = o.S ? o.S : default_S(dt);
+  const int B = o.B ? o.B : kDefaultB;
+  if (!(W == 4 || W == 8 || W == 16)) return SSS_ERR_UNSUPPORTED;
+  if (S < 1 || S > kMaxS || B < 1 || B > 4 || o.debug) return SSS_ERR_INVALID_VALUE;
+  const int WT = W * kWave;
+  std::vector<MatCtx> ctx((size_t)count);
+  std::vector<int64_t> bb((size_t)count + 1, 0), cb((size_t)count + 1, 0), sb((size_t)count + 1, 0);
+  int s_max = 1;
+  int64_t tot_m = 0, tot_n = 0, tot_nnz = 0, tot_tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    const sss_csr_desc &d = mats[i];
+    if (d.m < 0 || d.n < 0 || d.nnz < 0 || d.m >= INT_MAX || d.n >= INT_MAX || d.nnz >= INT_MAX)
+      return SSS_ERR_INVALID_VALUE;
+    if (d.m > 0 && (!d.row_ptr || !d.y)) return SSS_ERR_INVALID_VALUE;
+    if (d.nnz > 0 && (!d.col || !d.val || !d.x || misaligned(d.col) || misaligned(d.val))) return SSS_ERR_INVALID_VALUE;
+    const int Si = d.S ? d.S : S;
+    if (Si < 1 || Si > kMaxS) return SSS_ERR_INVALID_VALUE;
+    s_max = std::max(s_max, Si);
+    const int64_t nb = (d.m > 0 && d.nnz > 0) ? (d.nnz + (int64_t)Si * WT - 1) / ((int64_t)Si * WT) : 0;
+    MatCtx &c = ctx[(size_t)i];
+    c.row_ptr = d.row_ptr; c.col = d.col; c.val = d.val; c.x = d.x; c.y = d.y;
+    c.m = (int32_t)d.m; c.nnz = (int32_t)d.nnz; c.S = Si; c.W = W; c.n_bunches = nb;
+    c.n_tiles = d.nnz > 0 ? (d.nnz + WT - 1) / WT : 0;
+    c.dbg_start = nullptr; c.dbg_dirty = nullptr; c.dbg_heads = nullptr;
+    bb[(size_t)i + 1] = bb[(size_t)i] + nb;
+    cb[(size_t)i + 1] = cb[(size_t)i] + (nb + kWave - 1) / kWave;
+    sb[(size_t)i + 1] = sb[(size_t)i] + nb * Si;
+    tot_m += d.m; tot_n += d.n; tot_nnz += d.nnz; tot_tiles += c.n_tiles;
+  }
+  const int64_t nb_all = bb[(size_t)count], spec_all = sb[(size_t)count];
+  size_t off = 0;
+  const size_t o_mats = off; off = align256(off + sizeof(MatCtx) * (size_t)std::max(count, 1));
+  const size_t o_bb = off; off = align256(off + sizeof(int64_t) * ((size_t)count + 1));
+  const size_t o_cb = off; off = align256(off + sizeof(int64_t) * ((size_t)count + 1));
+  const size_t o_dm = off; off = align256(off + sizeof(uint32_t) * (size_t)(nb_all + 1));
+  const size_t o_sp = off; off = align256(off + sizeof(int4) * (size_t)(spec_all + 1));
+  const size_t o_si = off; off = align256(off + sizeof(int32_t) * (size_t)(nb_all + 1));
+  const size_t o_sv = off; off = align256(off + sizeof(double) * (size_t)(nb_all + 1));
+
+  sss_plan p = new sss_plan_s();
+  p->batch = true; p->dt = dt; p->W = W; p->S = S; p->B = B;
+  p->m = tot_m; p->n = tot_n; p->nnz = tot_nnz; p->n_tiles = tot_tiles; p->n_bunches = nb_all;
+  auto fail = [&](hipError_t e) {
+    g_last_hip = e;
+    if (p->aux) (void)hipFree(p->aux);
+    delete p;
+    return SSS_ERR_HIP;
+  };
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return fail(e);
+  e = hipMalloc(&p->aux, off);
+  if (e != hipSuccess) { p->aux = nullptr; return fail(e); }
+  e = hipMemset(p->aux, 0, off);
+  if (e != hipSuccess) return fail(e);
+  char *base = static_cast<char *>(p->aux);
+  for (int i = 0; i < count; ++i) {
+    MatCtx &c = ctx[(size_t)i];
+    c.dirty_mask = reinterpret_cast<uint32_t *>(base + o_dm) + bb[(size_t)i];
+    c.speculator = reinterpret_cast<int4 *>(base + o_sp) + sb[(size_t)i];
+    c.sync_idx = reinterpret_cast<int32_t *>(base + o_si) + bb[(size_t)i];
+    c.sync_val = reinterpret_cast<double *>(base + o_sv) + bb[(size_t)i];
+  }
+  if (count > 0) e = hipMemcpy(base + o_mats, ctx.data(), sizeof(MatCtx) * (size_t)count, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(base + o_bb, bb.data(), sizeof(int64_t) * ((size_t)count + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(base + o_cb, cb.data(), sizeof(int64_t) * ((size_t)count + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(e);
+  BatchArgs &ba = p->bargs;
+  ba.mats = reinterpret_cast<const MatCtx *>(base + o_mats);
+  ba.bunch_base = reinterpret_cast<const int64_t *>(base + o_bb);
+  ba.chunk_base = reinterpret_cast<const int64_t *>(base + o_cb);
+  ba.count = count;
+  ba.S_max = s_max;
+  ba.total_bunches = nb_all;
+  ba.total_chunks = cb[(size_t)count];
+  ba.total_waves = std::max<int64_t>(nb_all, count);
+  // persistent grids: as many workgroups as stay resident on the device
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess) return fail(e);
+  int per_cu1 = 0, per_cu2 = 0;
+  BatchFn k1 = pick_stage1_batch(dt, W);
+  const size_t lds1 = (size_t)B * stage1_lds_words(W, s_max) * sizeof(uint32_t);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, reinterpret_cast<const void *>(k1), B * kWave, lds1);
+  if (e != hipSuccess) return fail(e);
+  p->wpb2 = fixup_waves_per_block(W, dt);
+  const size_t lds2 = (size_t)p->wpb2 * WT * y_size(dt);
+  const void *k2 = dt == SSS_F64 ? reinterpret_cast<const void *>(sss_fixup_batch<double>)
+                                 : reinterpret_cast<const void *>(sss_fixup_batch<float>);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k2, p->wpb2 * kWave, lds2);
+  if (e != hipSuccess) return fail(e);
+  p->blocks1 = (int)std::max<int64_t>(1, std::min<int64_t>((nb_all + B - 1) / B, (int64_t)cus * std::max(per_cu1, 1)));
+  p->blocks2 = (int)std::max<int64_t>(
+      1, std::min<int64_t>((ba.total_waves + p->wpb2 - 1) / p->wpb2, (int64_t)cus * std::max(per_cu2, 1)));
+  *out = p;
+  return SSS_OK;
+}
+
+int sss_batch_execute(sss_plan p, void *stream) {
+  if (!p || !p->batch) return SSS_ERR_INVALID_VALUE;
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
+  return launch_batch(p, static_cast<hipStream_t>(stream));
+}
+
+int sss_batch_graph_launch(sss_plan p, void *stream) {
+  if (!p || !p->batch) return SSS_ERR_INVALID_VALUE;
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
+  if (!p->graph_exec) {
+    if (!p->capture_stream) SSS_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    SSS_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launch_batch(p, p->capture_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->capture_stream, &g);
+    if (rc != SSS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) { g_last_hip = e; return SSS_ERR_HIP; }
+    p->graph = g;
+    SSS_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+  }
+  SSS_HIP(hipGraphLaunch(p->graph_exec, static_cast<hipStream_t>(stream)));
+  return SSS_OK;
 }
 
 int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t *n_bunches) {
@@ -1003,6 +1263,7 @@ int sss_plan_debug_size(sss_plan p, size_t *bytes) {
 }
 
 int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes) {
+  if (p && p->batch) return SSS_ERR_INVALID_VALUE;
   size_t need = 0;
   int rc = sss_plan_debug_size(p, &need);
   if (rc != SSS_OK) return rc;

@@ -41,6 +41,12 @@ class SSSError(RuntimeError):
         self.status = status
 
 
+class CsrDesc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("S", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int), ("B", ctypes.c_int),
                 ("debug", ctypes.c_int)]
@@ -64,6 +70,10 @@ def lib():
         L.sss_csr_spmv_stage1.argtypes = [P, P, P, P, P, P, P]
         L.sss_csr_spmv_stage2.argtypes = [P, P, P, P]
         L.sss_plan_destroy.argtypes = [P]
+        L.sss_batch_plan_create.argtypes = [I, ctypes.POINTER(CsrDesc), I, ctypes.POINTER(PlanOpts), P,
+                                            ctypes.POINTER(P)]
+        L.sss_batch_execute.argtypes = [P, P]
+        L.sss_batch_graph_launch.argtypes = [P, P]
         L.sss_plan_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                     ctypes.POINTER(I64), ctypes.POINTER(I64)]
         L.sss_validate_csr.argtypes = [I64, I64, I64, P, P, P]
@@ -75,7 +85,8 @@ def lib():
         L.sss_version.restype = ctypes.c_char_p
         for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_plan_destroy",
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
-                  "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump"):
+                  "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
+                  "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -184,6 +195,50 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class BatchPlan:
+    """y_i = A_i x_i for many matrices in one persistent launch per stage
+    (sss_batch_plan_create).  `mats` is a list of (row_ptr, col, val, x, y, n)
+    device tensors (n = number of columns) or dicts with those keys and an
+    optional per-matrix "S".  The tensors must stay alive and in place for the
+    plan's lifetime."""
+
+    def __init__(self, mats, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0, stream=None):
+        L = lib()
+        self.dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+        descs = (CsrDesc * max(1, len(mats)))()
+        self._keep = []
+        for i, mt in enumerate(mats):
+            if not isinstance(mt, dict):
+                rp, col, val, x, y, n = mt
+                mt = {"row_ptr": rp, "col": col, "val": val, "x": x, "y": y, "n": n}
+            rp, col, val, x, y = mt["row_ptr"], mt["col"], mt["val"], mt["x"], mt["y"]
+            if val.dtype != _VALTYPE[self.dt] or x.dtype != _XTYPE[self.dt] or y.dtype != _XTYPE[self.dt]:
+                raise TypeError("val/x/y dtypes do not match the batch dtype")
+            m = rp.numel() - 1
+            d = descs[i]
+            d.m, d.n, d.nnz = m, int(mt["n"]), int(val.numel())
+            d.row_ptr, d.col, d.val, d.x, d.y = _ptr(rp), _ptr(col), _ptr(val), _ptr(x), _ptr(y)
+            d.S = int(mt.get("S", 0))
+            self._keep.append((rp, col, val, x, y))
+        opts = PlanOpts(MODE_FIXED, W, S, B, 0)
+        h = ctypes.c_void_p()
+        _check(L.sss_batch_plan_create(len(mats), descs, self.dt, ctypes.byref(opts), _stream(stream),
+                                       ctypes.byref(h)), "sss_batch_plan_create")
+        self._h = h
+
+    def info(self) -> dict:
+        return Plan.info(self)
+
+    def execute(self, stream=None):
+        _check(lib().sss_batch_execute(self._h, _stream(stream)), "sss_batch_execute")
+
+    def graph_launch(self, stream=None):
+        _check(lib().sss_batch_graph_launch(self._h, _stream(stream)), "sss_batch_graph_launch")
+
+    close = Plan.close
+    __del__ = Plan.__del__
 
 
 def csr_spmv(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,

@@ -1,0 +1,126 @@
+"""Batched path: many uneven matrices in one persistent launch per stage,
+eager and replayed from a HIP graph, each y_i against the oracle."""
+import numpy as np
+import pytest
+
+import csrgen
+import oracle
+from helpers import note, assert_exact, assert_f64_parity, csr_from_lengths
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1504_06474_amd import sss
+    sss.lib()
+    return torch
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    note(f"[gpu-test] {request.node.nodeid}")
+    yield
+
+
+def batch_set(int_valued):
+    """Uneven power-law matrices plus edge shapes: an all-empty matrix, a
+    matrix with nnz = 0, a single long row, leading/trailing empty rows."""
+    mats = csrgen.batched_set(count=24, m_lo=200, m_hi=6000, values="int" if int_valued else "uniform")
+    extra = [([0] * 50, 7), ([1], 1), ([30_000], 40_000), ([0] * 300 + [4, 0, 6] * 100 + [0] * 200, 50),
+             ([3, 1, 0, 0, 2] * 500, 900)]
+    for k, (lengths, n) in enumerate(extra):
+        mats.append(csr_from_lengths(lengths, n, seed=500 + k, int_valued=int_valued))
+    return mats
+
+
+def to_dev(torch, mats, dtype):
+    out = []
+    for A, x in mats:
+        out.append((torch.from_numpy(A.row_ptr).cuda(), torch.from_numpy(A.col).cuda(),
+                    torch.from_numpy(A.val).cuda().to(dtype), torch.from_numpy(x).cuda().to(dtype),
+                    torch.full((A.m,), float("nan"), dtype=dtype, device="cuda"), A.n))
+    return out
+
+
+@pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
+def test_batched_integer_exact(torch_cuda, WS):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    mats = batch_set(True)
+    dev = to_dev(torch, mats, torch.float64)
+    plan = sss.BatchPlan(dev, W=WS[0], S=WS[1])
+    plan.execute()
+    torch.cuda.synchronize()
+    for (A, x), d in zip(mats, dev):
+        assert_exact(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+def test_batched_per_matrix_S_and_tolerance(torch_cuda):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    mats = batch_set(False)
+    dev = to_dev(torch, mats, torch.float64)
+    descs = [{"row_ptr": d[0], "col": d[1], "val": d[2], "x": d[3], "y": d[4], "n": d[5], "S": 1 + (i % 7)}
+             for i, d in enumerate(dev)]
+    plan = sss.BatchPlan(descs, W=8)
+    plan.execute()
+    torch.cuda.synchronize()
+    for (A, x), d in zip(mats, dev):
+        assert_f64_parity(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x),
+                          oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
+
+
+def test_batched_graph_replays(torch_cuda):
+    """Replay the captured graph several times; between replays the program
+    does its own eager work (new x values, a clobbered y) and synchronises;
+    every replay must equal the eager result for the current x."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    mats = batch_set(True)
+    dev = to_dev(torch, mats, torch.float64)
+    plan = sss.BatchPlan(dev, W=8, S=2)
+    rng = np.random.default_rng(3)
+    for rep in range(4):
+        for (A, x), d in zip(mats, dev):
+            d[3].copy_(torch.from_numpy(rng.integers(-3, 4, A.n).astype(np.float64)))
+            d[4].fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.graph_launch()
+        torch.cuda.synchronize()
+        for (A, x), d in zip(mats, dev):
+            xh = d[3].cpu().numpy()
+            assert_exact(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, xh))
+        # eager run in between must agree too
+        plan.execute()
+        torch.cuda.synchronize()
+
+
+def test_batched_f32(torch_cuda):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    mats = batch_set(True)
+    dev = to_dev(torch, mats, torch.float32)
+    plan = sss.BatchPlan(dev, dtype=torch.float32, W=16, S=2)
+    plan.execute()
+    torch.cuda.synchronize()
+    for (A, x), d in zip(mats, dev):
+        assert_exact(d[4].double().cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+def test_batched_rejects_bad_descriptors(torch_cuda):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1()
+    rp = torch.from_numpy(A.row_ptr).cuda()
+    col = torch.from_numpy(A.col).cuda()
+    v = torch.from_numpy(A.val).cuda()
+    xx = torch.from_numpy(x).cuda()
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    colx = torch.empty(A.nnz + 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(sss.SSSError):
+        sss.BatchPlan([(rp, colx[1:], v, xx, y, A.n)])
+    with pytest.raises(sss.SSSError):
+        sss.BatchPlan([{"row_ptr": rp, "col": col, "val": v, "x": xx, "y": y, "n": A.n, "S": 99}])
