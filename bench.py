@@ -159,6 +159,122 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
     return out
 
 
+def batched_block(torch, sss, steps: int, warmup: int) -> dict:
+    """512 uneven power-law matrices: one batched plan (one persistent launch
+    per stage, eager and as a replayed HIP graph) against 512 separate plans
+    launched one after another (eager and captured in a graph)."""
+    import csrgen
+    import oracle
+    log("[bench] batched: generating 512 matrices (seeds 20000..20511)")
+    mats = csrgen.batched_set(512)
+    out = {"workload": "batch512_zipf2", "count": len(mats), "sum_m": int(sum(A.m for A, _ in mats)),
+           "sum_nnz": int(sum(A.nnz for A, _ in mats))}
+    refs = [oracle.spmv(A.row_ptr, A.col, A.val, x) for A, x in mats]
+    scales = [oracle.abs_spmv(A.row_ptr, A.col, A.val, x) for A, x in mats]
+
+    def timed(fn, k):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    for kind, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        dev = []
+        for A, x in mats:
+            dev.append((torch.from_numpy(A.row_ptr).cuda(), torch.from_numpy(A.col).cuda(),
+                        torch.from_numpy(A.val).cuda().to(tdt), torch.from_numpy(x).cuda().to(tdt),
+                        torch.empty(A.m, dtype=tdt, device="cuda"), A.n))
+        bp = sss.BatchPlan(dev, dtype=tdt)
+        info = bp.info()
+        ms_batch = timed(bp.execute, steps)
+        ms_graph = timed(bp.graph_launch, steps)
+        # correctness of the batched result (every matrix, every row)
+        worst = 0.0
+        for (A, x), d, ref, sc in zip(mats, dev, refs, scales):
+            err = np.abs(d[4].double().cpu().numpy() - ref)
+            nz = sc > 0
+            if nz.any():
+                worst = max(worst, float((err[nz] / sc[nz]).max()))
+        plans = [sss.Plan(A.m, A.n, A.nnz, dtype=tdt) for A, _ in mats]
+
+        def separate():
+            for pl, d in zip(plans, dev):
+                pl.execute(d[0], d[1], d[2], d[3], d[4])
+
+        ms_sep = timed(separate, max(3, steps // 4))
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            separate()
+        torch.cuda.current_stream().wait_stream(side)
+        with torch.cuda.graph(g):
+            separate()
+        ms_sep_graph = timed(g.replay, max(3, steps // 4))
+        vb = 8 if kind == "f64" else 4
+        byts = sum(alg_bytes(A.m, A.n, A.nnz, vb, vb) for A, _ in mats)
+        out[kind] = {"W": info["W"], "S": info["S"], "n_bunches": info["n_bunches"],
+                     "batched_us": round(ms_batch * 1e3, 1), "batched_graph_us": round(ms_graph * 1e3, 1),
+                     "separate_us": round(ms_sep * 1e3, 1), "separate_graph_us": round(ms_sep_graph * 1e3, 1),
+                     "speedup_vs_separate": round(ms_sep / ms_batch, 2),
+                     "speedup_vs_separate_graph": round(ms_sep_graph / ms_batch, 2),
+                     "batched_GFLOPs": round(2 * out["sum_nnz"] / (ms_batch * 1e-3) / 1e9, 1),
+                     "batched_alg_GBps": round(byts / (ms_batch * 1e-3) / 1e9, 1),
+                     "max_err_scaled_vs_f64_oracle": worst}
+        log(f"[bench] batched {kind}: {out[kind]}")
+        del g, plans, bp, dev
+        torch.cuda.synchronize()
+    return out
+
+
+def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
+    """The trained selector on held-out selector matrices (indices 2000.., not
+    trained on): regret against the grid timed here, gain over the default
+    parameters (W = 8, S = 5); and its pick for the benchmark matrix."""
+    from csrgen.torch_gen import selector_matrix_gpu
+    if not sss.load_selector():
+        return {"error": "no trained selector parameters"}
+
+    from paper_1504_06474_amd.selector_train import time_plan as t_plan
+
+    ratios, gains, hits, misses = [], [], 0, []
+    for i in range(2000, 2000 + n_matrices):
+        d = selector_matrix_gpu(i)
+        args = (d["row_ptr"], d["col"], d["val"], d["x"], torch.empty(d["m"], dtype=torch.float64, device="cuda"))
+        grid, best = sss.autotune(*args, n=d["n"], reps=5)
+        cls = sss.selector_predict(sss.features(d["row_ptr"], d["n"], d["nnz"]))
+        W, S = sss.class_params(cls)
+        p_def = sss.Plan(d["m"], d["n"], d["nnz"], W=8, S=5)
+        p_sel = sss.Plan(d["m"], d["n"], d["nnz"], W=W, S=S)
+        t_def, t_sel = t_plan(p_def, args, 5), t_plan(p_sel, args, 5)
+        p_def.close()
+        p_sel.close()
+        ratios.append(grid[cls] / grid.min())
+        gains.append(t_def / t_sel)
+        hits += int(cls == best)
+        if ratios[-1] > 1.1:
+            misses.append({"i": i, "name": d["name"], "picked": [W, S], "best": list(sss.class_params(best)),
+                           "picked_us": round(float(grid[cls]), 1), "best_us": round(float(grid.min()), 1)})
+        del d, args
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))
+    out = {"held_out_matrices": n_matrices, "regret_vs_grid": round(gm(ratios) - 1, 4),
+           "gain_vs_default": round(gm(gains), 3), "top1": round(hits / n_matrices, 3),
+           "worst_ratio": round(float(max(ratios)), 3), "picks_over_10pct": misses}
+    rp, col, v, xx, y, A = bench_matrix
+    grid, best = sss.autotune(rp, col, v, xx, y, n=A.n, reps=5)
+    cls = sss.selector_predict(sss.features(rp, A.n, A.nnz))
+    out["benchmark_matrix"] = {"selected": list(sss.class_params(cls)), "selected_us": round(float(grid[cls]), 2),
+                               "grid_best": list(sss.class_params(best)), "grid_best_us": round(float(grid.min()), 2)}
+    log(f"[bench] selector: {out}")
+    return out
+
+
 def run_copy_calibration(steps: int):
     import torch
     nbytes = 1 << 30
@@ -191,6 +307,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["spmv", "copy"], default="spmv")
     ap.add_argument("--skip-precision", action="store_true", help="skip the FP32/BF16 comparison")
+    ap.add_argument("--skip-batched", action="store_true", help="skip the 512-matrix batched comparison")
+    ap.add_argument("--skip-selector", action="store_true", help="skip the tile-selector evaluation")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -320,9 +438,13 @@ def main():
             "sampled_max_rel_err": max_rel,
         },
     }
+    if not args.skip_selector:
+        out["extras"]["selector"] = selector_block(torch, sss, 40, copies[0] + (A,))
+    del copies
     if not args.skip_precision:
-        del copies
         out["extras"]["precision"] = precision_block(torch, sss, min(args.steps, 50), min(args.warmup, 5))
+    if not args.skip_batched:
+        out["extras"]["batched"] = batched_block(torch, sss, min(args.steps, 20), 2)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, x, args.cpu_seconds)

@@ -61,11 +61,20 @@ typedef enum {
  * thread-bunches, and the fixup sums, in double. */
 typedef enum { SSS_F64 = 0, SSS_F32 = 1, SSS_BF16 = 2 } sss_dtype;
 
-/* How a plan chooses (W, S): FIXED takes opts.W/S/B; GRID times every class of
- * the parameter grid on the caller's matrix and keeps the fastest; SELECTOR
- * asks the trained selector network (falling back to the defaults if none is
- * loaded). */
+/* How a plan chooses (W, S): FIXED takes opts.W/S/B; SELECTOR computes the
+ * matrix features from row_ptr on the device and asks the selector network
+ * loaded with sss_selector_set (the defaults when none is loaded).  The grid
+ * search (GRID) needs the whole matrix and x: it is sss_csr_spmv_autotune,
+ * whose best class then goes to a FIXED plan; plan_create rejects GRID. */
 typedef enum { SSS_MODE_SELECTOR = 0, SSS_MODE_GRID = 1, SSS_MODE_FIXED = 2 } sss_mode;
+
+/* The parameter grid: class c has W = {4, 8, 16}[c / 4], S = {1, 2, 4, 8}[c % 4]
+ * (T = 64 and B = 2).  Section 3.4 / Table 3 choose W and S per processor
+ * empirically; here they are chosen per matrix. */
+#define SSS_N_CLASSES 12
+#define SSS_N_FEATURES 8
+#define SSS_MLP_HIDDEN 64
+#define SSS_MLP_PARAMS 5516
 
 typedef struct {
   int mode;  /* sss_mode */
@@ -181,6 +190,60 @@ int sss_plan_debug_size(sss_plan p, size_t *bytes);
  *   double sync_val[n_bunches]
  * Section 3.2 and the appendix algorithm define these arrays. */
 int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes);
+
+/* ---------------------------------------------------------------------------
+ * Parameter selection
+ * ------------------------------------------------------------------------- */
+
+/* (W, S) of grid class cls (host integers). */
+int sss_class_params(int cls, int *W, int *S);
+
+/* Matrix features from row_ptr (device), one pass on `stream`, which this call
+ * synchronises; feats is HOST float[8]:
+ *   log2(m+1), log2(n+1), log2(nnz+1), log2(1+mean row length),
+ *   log2(1+row-length variance), log2(1+max row length), empty-row fraction,
+ *   bytes per stored value (8, 4 or 2 for F64, F32, BF16). */
+int sss_csr_features(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, sss_dtype dt, void *stream,
+                     float *feats);
+
+/* Grid autotuner: times y = A x for every class (after two warm-up runs of
+ * each class, five rounds over the classes in turn, each a trial of `reps`
+ * back-to-back runs between HIP events on `stream`; per class the median
+ * trial's mean), writes microseconds per run for each class to HOST
+ * class_us[12] (may be NULL) and the fastest class to *best_class.
+ * Device arguments as for execute; y is overwritten.  Allocates plans and
+ * synchronises. */
+int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                          const void *val, const void *x, void *y, sss_dtype dt, int reps, void *stream,
+                          float *class_us, int *best_class);
+
+/* Selector network 8 -> 64 -> 64 -> 12 (ReLU), FP32 parameters packed as
+ * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][12], b3[12] (W[i][o]: input i
+ * to output o).  All arrays DEVICE float unless stated; N samples, row-major.
+ *   forward:  H1 = relu(X W1 + b1), H2 = relu(H1 W2 + b2), Z = H2 W3 + b3
+ *   backward: softmax cross-entropy of Z against target distributions Q
+ *             [N][12], mean over samples: the gradient (packed like params)
+ *             and optionally the per-sample loss [N]; work holds N*140 floats
+ *   adam:     one Adam step (bias-corrected, step >= 1) on n parameters
+ * Each only enqueues on `stream`.  These train the selector (on the
+ * autotuner's timings) and run its inference. */
+int sss_mlp_forward(const float *params, const float *X, int N, float *H1, float *H2, float *Z, void *stream);
+int sss_mlp_backward(const float *params, const float *X, const float *H1, const float *H2, const float *Z,
+                     const float *Q, int N, float *grad, float *loss, float *work, void *stream);
+int sss_mlp_adam(float *params, const float *grad, float *m1, float *m2, int n, int step, float lr, float beta1,
+                 float beta2, float eps, void *stream);
+
+/* Load a trained selector for the current device: HOST params[5516] and the
+ * feature normalisation (x - mean) / std, HOST float[8] each.  Copies them;
+ * allocates on first use and keeps the device copy until the process ends. */
+int sss_selector_set(const float *params, const float *mean, const float *stdv);
+
+/* Class the loaded selector picks for HOST features[8] (forward kernels on the
+ * device, synchronous).  SSS_ERR_UNSUPPORTED if no selector is loaded. */
+int sss_selector_predict(const float *feats, int *cls);
+
+/* 1 if a selector is loaded on the current device. */
+int sss_selector_loaded(void);
 
 /* Human-readable status; sss_last_hip_error the last HIP failure (thread). */
 const char *sss_status_string(int status);

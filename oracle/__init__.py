@@ -25,6 +25,11 @@ import subprocess
 
 import numpy as np
 
+# OpenMP worker threads of the oracle sleep between calls instead of spinning:
+# spinning threads compete with the thread that launches GPU work and distort
+# GPU timings taken in the same process.  (Read by libgomp when it loads.)
+os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "csr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")

@@ -999,18 +999,30 @@ extern "C" {
 
 int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, sss_dtype dt,
                              const sss_plan_opts *opts, void *stream, sss_plan *out) {
-  (void)row_ptr;
-  (void)stream;
   if (!out) return SSS_ERR_INVALID_VALUE;
   *out = nullptr;
   if (m < 0 || n < 0 || nnz < 0 || m >= INT_MAX || n >= INT_MAX || nnz >= INT_MAX) return SSS_ERR_INVALID_VALUE;
   if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
   sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
   if (opts) o = *opts;
-  if (o.mode != SSS_MODE_FIXED) return SSS_ERR_UNSUPPORTED;
-  const int W = o.W ? o.W : default_W(dt);
-  const int S = o.S ? o.S : default_S(dt);
+  if (o.mode != SSS_MODE_FIXED && o.mode != SSS_MODE_SELECTOR) return SSS_ERR_UNSUPPORTED;
+  int W = o.W ? o.W : default_W(dt);
+  int S = o.S ? o.S : default_S(dt);
   const int B = o.B ? o.B : kDefaultB;
+  if (o.mode == SSS_MODE_SELECTOR && m > 0 && nnz > 0) {
+    if (!row_ptr) return SSS_ERR_INVALID_VALUE;
+    if (sss_selector_loaded()) {
+      float f[SSS_N_FEATURES];
+      int cls = 0;
+      int rc = sss_csr_features(m, n, nnz, row_ptr, dt, stream, f);
+      if (rc == SSS_OK) rc = sss_selector_predict(f, &cls);
+      if (rc == SSS_OK) rc = sss_class_params(cls, &W, &S);
+      if (rc != SSS_OK) return rc;
+    } else {
+      W = default_W(dt);
+      S = default_S(dt);
+    }
+  }
   if (!(W == 4 || W == 8 || W == 16)) return SSS_ERR_UNSUPPORTED;
   if (S < 1 || S > kMaxS || B < 1 || B > 4) return SSS_ERR_INVALID_VALUE;
   sss_plan p = new sss_plan_s();

@@ -1,0 +1,198 @@
+"""Train and evaluate the tile/parameter selector on one GPU.
+
+    python -m paper_1504_06474_amd.selector_train --out <out-dir> \
+        [--train 2000] [--test 200] [--reps 5] [--steps 4000]
+
+1. Data: matrices 0..train+test-1 of the selector set (2D 5-point and 3D
+   27-point stencils, FEM-like bands, web-like lognormal rows, dense rows in a
+   sparse matrix; 1e4..2e6 rows), drawn on the GPU.  For each: the 8 features
+   (sss_csr_features) and the median time of every (W, S) class of the grid
+   (sss_csr_spmv_autotune, `reps` timed runs each), plus the time of the
+   default parameters (W = 8, S = 5: the paper's Table 3 choice for double
+   precision on its AMD GPU).
+2. Training on the first `train` matrices: features z-scored, soft targets
+   q_c ~ exp(-(t_c / t_best - 1) / tau), softmax cross-entropy, full-batch
+   Adam -- forward, backward and update all by the library's HIP kernels.
+3. Evaluation on the last `test` matrices against the grid timed in the same
+   session: regret = geomean(t(selected) / t(grid best)) - 1, gain =
+   geomean(t(default) / t(selected)).
+Writes selector_params.json (parameters, normalisation, class table) and
+selector_report.json (metrics, per-class breakdown) to --out; the dataset goes
+to dataset.npz there.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import sss
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def time_plan(plan, args, reps: int, trials: int = 5) -> float:
+    """Microseconds per run: two warm-up runs, then `trials` trials of `reps`
+    back-to-back runs between two events; the median trial (the autotuner's
+    protocol for one class)."""
+    plan.execute(*args)
+    plan.execute(*args)
+    ts = []
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.execute(*args)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3 / reps)
+    return float(np.median(ts))
+
+
+def collect(indices, reps: int, default_ws=(8, 5)):
+    from csrgen.torch_gen import selector_matrix_gpu
+    feats, times, t_def, names, sizes = [], [], [], [], []
+    t0 = time.time()
+    for k, i in enumerate(indices):
+        d = selector_matrix_gpu(int(i))
+        rp, col, val, x = d["row_ptr"], d["col"], d["val"], d["x"]
+        y = torch.empty(d["m"], dtype=torch.float64, device="cuda")
+        feats.append(sss.features(rp, d["n"], d["nnz"], torch.float64))
+        t, _ = sss.autotune(rp, col, val, x, y, d["n"], reps)
+        times.append(t)
+        plan = sss.Plan(d["m"], d["n"], d["nnz"], W=default_ws[0], S=default_ws[1])
+        t_def.append(time_plan(plan, (rp, col, val, x, y), reps))
+        plan.close()
+        names.append(d["cls"])
+        sizes.append((d["m"], d["nnz"]))
+        del d, rp, col, val, x, y
+        if (k + 1) % 50 == 0:
+            log(f"[selector] {k + 1}/{len(indices)} matrices timed ({time.time() - t0:.0f} s)")
+    return (np.array(feats, dtype=np.float32), np.array(times), np.array(t_def), np.array(names),
+            np.array(sizes, dtype=np.int64))
+
+
+def soft_targets(times: np.ndarray, tau: float) -> np.ndarray:
+    r = times / times.min(axis=1, keepdims=True) - 1.0
+    q = np.exp(-r / tau)
+    return q / q.sum(axis=1, keepdims=True)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, packed W1 b1 W2 b2 W3 b3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = [(8, 64), (64,), (64, 64), (64,), (64, 12), (12,)]
+    parts = [rng.normal(0, math.sqrt(2.0 / s[0]), size=s) if len(s) == 2 else np.zeros(s) for s in shapes]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def train(X: np.ndarray, Q: np.ndarray, steps: int, lr: float, seed: int):
+    N = X.shape[0]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    P = dev(init_params(seed))
+    Xd, Qd = dev(X), dev(Q)
+    H1 = torch.empty(N, 64, device="cuda")
+    H2 = torch.empty(N, 64, device="cuda")
+    Z = torch.empty(N, 12, device="cuda")
+    g = torch.empty(sss.MLP_PARAMS, device="cuda")
+    loss = torch.empty(N, device="cuda")
+    work = torch.empty(N * 140, device="cuda")
+    m1 = torch.zeros(sss.MLP_PARAMS, device="cuda")
+    m2 = torch.zeros(sss.MLP_PARAMS, device="cuda")
+    hist = []
+    for step in range(1, steps + 1):
+        sss.mlp_forward(P, Xd, H1, H2, Z)
+        sss.mlp_backward(P, Xd, H1, H2, Z, Qd, g, loss, work)
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * (step - 1) / steps))  # cosine decay
+        sss.mlp_adam(P, g, m1, m2, step, lr_t)
+        if step % 500 == 0 or step == 1:
+            hist.append((step, float(loss.mean())))
+    torch.cuda.synchronize()
+    return P.cpu().numpy(), hist
+
+
+def predict(params: np.ndarray, X: np.ndarray) -> np.ndarray:
+    N = X.shape[0]
+    P = torch.from_numpy(params).cuda()
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    H1 = torch.empty(N, 64, device="cuda")
+    H2 = torch.empty(N, 64, device="cuda")
+    Z = torch.empty(N, 12, device="cuda")
+    sss.mlp_forward(P, Xd, H1, H2, Z)
+    torch.cuda.synchronize()
+    return Z.cpu().numpy().argmax(axis=1)
+
+
+def geomean(a) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    return float(np.exp(np.log(a).mean()))
+
+
+def evaluate(pred: np.ndarray, times: np.ndarray, t_def: np.ndarray, names: np.ndarray) -> dict:
+    t_sel = times[np.arange(len(pred)), pred]
+    t_best = times.min(axis=1)
+    out = {"n": int(len(pred)), "regret": geomean(t_sel / t_best) - 1.0,
+           "gain_vs_default": geomean(t_def / t_sel), "grid_gain_vs_default": geomean(t_def / t_best),
+           "accuracy": float((pred == times.argmin(axis=1)).mean()),
+           "worst_ratio": float((t_sel / t_best).max()), "per_class": {}}
+    for c in sorted(set(names.tolist())):
+        k = names == c
+        out["per_class"][c] = {"n": int(k.sum()), "regret": geomean(t_sel[k] / t_best[k]) - 1.0,
+                               "gain_vs_default": geomean(t_def[k] / t_sel[k])}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--test", type=int, default=200)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--tau", type=float, default=0.03)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+    sss.lib()
+    n_all = args.train + args.test
+    log(f"[selector] timing {n_all} matrices, {sss.N_CLASSES} classes, {args.reps} runs each")
+    feats, times, t_def, names, sizes = collect(range(n_all), args.reps)
+    np.savez(os.path.join(args.out, "dataset.npz"), feats=feats, times=times, t_default=t_def, names=names,
+             sizes=sizes)
+    Xtr, Xte = feats[:args.train], feats[args.train:]
+    mean = Xtr.mean(axis=0)
+    std = Xtr.std(axis=0)
+    std[std == 0] = 1.0
+    Q = soft_targets(times[:args.train], args.tau)
+    params, hist = train((Xtr - mean) / std, Q, args.steps, args.lr, args.seed)
+    log(f"[selector] loss {hist}")
+    res_tr = evaluate(predict(params, (Xtr - mean) / std), times[:args.train], t_def[:args.train],
+                      names[:args.train])
+    res_te = evaluate(predict(params, (Xte - mean) / std), times[args.train:], t_def[args.train:],
+                      names[args.train:])
+    classes = [list(sss.class_params(c)) for c in range(sss.N_CLASSES)]
+    json.dump({"params": [float(v) for v in params], "feature_mean": [float(v) for v in mean],
+               "feature_std": [float(v) for v in std], "classes_WS": classes,
+               "features": ["log2(m+1)", "log2(n+1)", "log2(nnz+1)", "log2(1+mean)", "log2(1+var)",
+                            "log2(1+max)", "empty_frac", "bytes_per_value"],
+               "trained_on": f"selector matrices 0..{args.train - 1} (seed base 10000), FP64, T=64 B=2",
+               "command": "python -m paper_1504_06474_amd.selector_train " + " ".join(sys.argv[1:])},
+              open(os.path.join(args.out, "selector_params.json"), "w"))
+    report = {"train": res_tr, "test": res_te, "loss_history": hist, "args": vars(args),
+              "class_best_counts": np.bincount(times.argmin(axis=1), minlength=12).tolist()}
+    json.dump(report, open(os.path.join(args.out, "selector_report.json"), "w"), indent=1)
+    log(f"[selector] test regret {res_te['regret']:.4f} gain {res_te['gain_vs_default']:.3f} "
+        f"(grid gain {res_te['grid_gain_vs_default']:.3f}) accuracy {res_te['accuracy']:.3f}")
+
+
+if __name__ == "__main__":
+    main()

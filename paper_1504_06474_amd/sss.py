@@ -73,6 +73,16 @@ def lib():
         L.sss_batch_plan_create.argtypes = [I, ctypes.POINTER(CsrDesc), I, ctypes.POINTER(PlanOpts), P,
                                             ctypes.POINTER(P)]
         L.sss_batch_execute.argtypes = [P, P]
+        FP = ctypes.POINTER(ctypes.c_float)
+        L.sss_class_params.argtypes = [I, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
+        L.sss_csr_spmv_autotune.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, FP, ctypes.POINTER(I)]
+        L.sss_mlp_forward.argtypes = [P, P, I, P, P, P, P]
+        L.sss_mlp_backward.argtypes = [P, P, P, P, P, P, I, P, P, P, P]
+        L.sss_mlp_adam.argtypes = [P, P, P, P, I, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, P]
+        L.sss_selector_set.argtypes = [FP, FP, FP]
+        L.sss_selector_predict.argtypes = [FP, ctypes.POINTER(I)]
         L.sss_batch_graph_launch.argtypes = [P, P]
         L.sss_plan_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                     ctypes.POINTER(I64), ctypes.POINTER(I64)]
@@ -86,7 +96,10 @@ def lib():
         for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_plan_destroy",
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
-                  "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch"):
+                  "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
+                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_mlp_forward",
+                  "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
+                  "sss_selector_loaded"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -239,6 +252,85 @@ class BatchPlan:
 
     close = Plan.close
     __del__ = Plan.__del__
+
+
+# ---------------------------------------------------------------- selection
+
+N_CLASSES, N_FEATURES, MLP_PARAMS = 12, 8, 5516
+
+
+def class_params(cls: int):
+    W, S = ctypes.c_int(), ctypes.c_int()
+    _check(lib().sss_class_params(int(cls), ctypes.byref(W), ctypes.byref(S)), "sss_class_params")
+    return W.value, S.value
+
+
+def features(row_ptr: torch.Tensor, n: int, nnz: int, dtype=torch.float64, stream=None) -> np.ndarray:
+    """The 8 selector features of a CSR matrix (sss_csr_features)."""
+    f = (ctypes.c_float * N_FEATURES)()
+    dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    _check(lib().sss_csr_features(row_ptr.numel() - 1, int(n), int(nnz), _ptr(row_ptr), dt, _stream(stream), f),
+           "sss_csr_features")
+    return np.array(f[:], dtype=np.float32)
+
+
+def autotune(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None):
+    """Median microseconds of every grid class and the fastest class
+    (sss_csr_spmv_autotune)."""
+    t = (ctypes.c_float * N_CLASSES)()
+    best = ctypes.c_int()
+    dt = _DTYPES[val.dtype]
+    _check(lib().sss_csr_spmv_autotune(row_ptr.numel() - 1, int(n), val.numel(), _ptr(row_ptr), _ptr(col),
+                                       _ptr(val), _ptr(x), _ptr(y), dt, int(reps), _stream(stream), t,
+                                       ctypes.byref(best)), "sss_csr_spmv_autotune")
+    return np.array(t[:], dtype=np.float64), best.value
+
+
+def mlp_forward(params, X, H1, H2, Z, stream=None):
+    _check(lib().sss_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(H1), _ptr(H2), _ptr(Z), _stream(stream)),
+           "sss_mlp_forward")
+
+
+def mlp_backward(params, X, H1, H2, Z, Q, grad, loss, work, stream=None):
+    _check(lib().sss_mlp_backward(_ptr(params), _ptr(X), _ptr(H1), _ptr(H2), _ptr(Z), _ptr(Q), X.shape[0],
+                                  _ptr(grad), _ptr(loss), _ptr(work), _stream(stream)), "sss_mlp_backward")
+
+
+def mlp_adam(params, grad, m1, m2, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().sss_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), params.numel(), int(step), lr, beta1,
+                              beta2, eps, _stream(stream)), "sss_mlp_adam")
+
+
+def selector_set(params: np.ndarray, mean: np.ndarray, std: np.ndarray):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    mu = np.ascontiguousarray(mean, dtype=np.float32)
+    sd = np.ascontiguousarray(std, dtype=np.float32)
+    FP = ctypes.POINTER(ctypes.c_float)
+    _check(lib().sss_selector_set(p.ctypes.data_as(FP), mu.ctypes.data_as(FP), sd.ctypes.data_as(FP)),
+           "sss_selector_set")
+
+
+def selector_predict(feats: np.ndarray) -> int:
+    f = np.ascontiguousarray(feats, dtype=np.float32)
+    c = ctypes.c_int()
+    _check(lib().sss_selector_predict(f.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(c)),
+           "sss_selector_predict")
+    return c.value
+
+
+SELECTOR_FILE = os.path.join(HERE, "selector_params.json")
+
+
+def load_selector(path: Optional[str] = None) -> bool:
+    """Load the trained selector shipped with the package (or `path`) onto the
+    current device.  Returns False if there is no such file."""
+    import json
+    path = path or SELECTOR_FILE
+    if not os.path.exists(path):
+        return False
+    d = json.load(open(path))
+    selector_set(np.array(d["params"]), np.array(d["feature_mean"]), np.array(d["feature_std"]))
+    return True
 
 
 def csr_spmv(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,
