@@ -235,37 +235,48 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
 
 def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
     """The trained selector on held-out selector matrices (indices 2000.., not
-    trained on): regret against the grid timed here, gain over the default
-    parameters (W = 8, S = 5); and its pick for the benchmark matrix."""
+    trained on), each stored as FP64, FP32 and BF16: regret against the grid
+    timed here, gain over the default parameters of that value type; and its
+    pick for the benchmark matrix."""
     from csrgen.torch_gen import selector_matrix_gpu
     if not sss.load_selector():
         return {"error": "no trained selector parameters"}
 
-    from paper_1504_06474_amd.selector_train import time_plan as t_plan
+    from paper_1504_06474_amd.selector_train import VALUE_TYPES, time_plan as t_plan
 
-    ratios, gains, hits, misses = [], [], 0, []
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))
+    acc = {k: {"ratios": [], "gains": [], "hits": 0, "misses": []} for k in VALUE_TYPES}
     for i in range(2000, 2000 + n_matrices):
         d = selector_matrix_gpu(i)
-        args = (d["row_ptr"], d["col"], d["val"], d["x"], torch.empty(d["m"], dtype=torch.float64, device="cuda"))
-        grid, best = sss.autotune(*args, n=d["n"], reps=5)
-        cls = sss.selector_predict(sss.features(d["row_ptr"], d["n"], d["nnz"]))
-        W, S = sss.class_params(cls)
-        p_def = sss.Plan(d["m"], d["n"], d["nnz"], W=8, S=5)
-        p_sel = sss.Plan(d["m"], d["n"], d["nnz"], W=W, S=S)
-        t_def, t_sel = t_plan(p_def, args, 5), t_plan(p_sel, args, 5)
-        p_def.close()
-        p_sel.close()
-        ratios.append(grid[cls] / grid.min())
-        gains.append(t_def / t_sel)
-        hits += int(cls == best)
-        if ratios[-1] > 1.1:
-            misses.append({"i": i, "name": d["name"], "picked": [W, S], "best": list(sss.class_params(best)),
-                           "picked_us": round(float(grid[cls]), 1), "best_us": round(float(grid.min()), 1)})
-        del d, args
-    gm = lambda a: float(np.exp(np.mean(np.log(a))))
-    out = {"held_out_matrices": n_matrices, "regret_vs_grid": round(gm(ratios) - 1, 4),
-           "gain_vs_default": round(gm(gains), 3), "top1": round(hits / n_matrices, 3),
-           "worst_ratio": round(float(max(ratios)), 3), "picks_over_10pct": misses}
+        for kind, (vt, xt) in VALUE_TYPES.items():
+            a = acc[kind]
+            args = (d["row_ptr"], d["col"], d["val"].to(vt), d["x"].to(xt),
+                    torch.empty(d["m"], dtype=xt, device="cuda"))
+            grid, best = sss.autotune(*args, n=d["n"], reps=5)
+            cls = sss.selector_predict(sss.features(d["row_ptr"], d["n"], d["nnz"], vt))
+            W, S = sss.class_params(cls)
+            p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt)
+            p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, W=W, S=S)
+            t_def, t_sel = t_plan(p_def, args, 5), t_plan(p_sel, args, 5)
+            p_def.close()
+            p_sel.close()
+            a["ratios"].append(grid[cls] / grid.min())
+            a["gains"].append(t_def / t_sel)
+            a["hits"] += int(cls == best)
+            if a["ratios"][-1] > 1.1:
+                a["misses"].append({"i": i, "name": d["name"], "picked": [W, S],
+                                    "best": list(sss.class_params(best)), "picked_us": round(float(grid[cls]), 1),
+                                    "best_us": round(float(grid.min()), 1)})
+            del args
+        del d
+    out = {"held_out_matrices": n_matrices}
+    for kind, a in acc.items():
+        out[kind] = {"regret_vs_grid": round(gm(a["ratios"]) - 1, 4), "gain_vs_default": round(gm(a["gains"]), 3),
+                     "top1": round(a["hits"] / n_matrices, 3), "worst_ratio": round(float(max(a["ratios"])), 3),
+                     "picks_over_10pct": a["misses"]}
+    allr = [r for a in acc.values() for r in a["ratios"]]
+    out["regret_vs_grid"] = round(gm(allr) - 1, 4)
+    out["gain_vs_default"] = round(gm([g for a in acc.values() for g in a["gains"]]), 3)
     rp, col, v, xx, y, A = bench_matrix
     grid, best = sss.autotune(rp, col, v, xx, y, n=A.n, reps=5)
     cls = sss.selector_predict(sss.features(rp, A.n, A.nnz))

@@ -64,8 +64,8 @@ typedef enum { SSS_F64 = 0, SSS_F32 = 1, SSS_BF16 = 2 } sss_dtype;
 /* How a plan chooses (W, S): FIXED takes opts.W/S/B; SELECTOR computes the
  * matrix features from row_ptr on the device and asks the selector network
  * loaded with sss_selector_set (the defaults when none is loaded).  The grid
- * search (GRID) needs the whole matrix and x: it is sss_csr_spmv_autotune,
- * whose best class then goes to a FIXED plan; plan_create rejects GRID. */
+ * search (GRID) needs the whole matrix and x, so it has a call of its own,
+ * sss_csr_spmv_plan_create_grid; plan_create rejects GRID. */
 typedef enum { SSS_MODE_SELECTOR = 0, SSS_MODE_GRID = 1, SSS_MODE_FIXED = 2 } sss_mode;
 
 /* The parameter grid: class c has W = {4, 8, 16}[c / 4], S = {1, 2, 4, 8}[c % 4]
@@ -216,6 +216,15 @@ int sss_csr_features(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, 
 int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
                           const void *val, const void *x, void *y, sss_dtype dt, int reps, void *stream,
                           float *class_us, int *best_class);
+
+/* GRID-mode plan (the selector's fallback, and the judge of its regret):
+ * runs sss_csr_spmv_autotune on the caller's matrix and returns in *out a
+ * plan with the fastest class's (W, S) and the default B.  Arguments as for
+ * sss_csr_spmv_autotune; y is overwritten; *out is NULL on any error.
+ * Allocates and synchronises (a planning call, not for a timed loop). */
+int sss_csr_spmv_plan_create_grid(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                                  const void *val, const void *x, void *y, sss_dtype dt, int reps, void *stream,
+                                  sss_plan *out);
 
 /* Selector network 8 -> 64 -> 64 -> 12 (ReLU), FP32 parameters packed as
  * W1[8][64], b1[64], W2[64][64], b2[64], W3[64][12], b3[12] (W[i][o]: input i

@@ -375,6 +375,22 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
   return SSS_OK;
 }
 
+int sss_csr_spmv_plan_create_grid(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                                  const void *val, const void *x, void *y, sss_dtype dt, int reps, void *stream,
+                                  sss_plan *out) {
+  if (!out) return SSS_ERR_INVALID_VALUE;
+  *out = nullptr;
+  sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
+  if (m > 0 && nnz > 0) {
+    int best = 0;
+    const int rc = sss_csr_spmv_autotune(m, n, nnz, row_ptr, col, val, x, y, dt, reps, stream, nullptr, &best);
+    if (rc != SSS_OK) return rc;
+    o.W = kClassW[best];
+    o.S = kClassS[best];
+  }
+  return sss_csr_spmv_plan_create(m, n, nnz, row_ptr, dt, &o, stream, out);
+}
+
 const char *sss_selector_last_hip_error(void) { return hipGetErrorString(g_sel_hip); }
 
 }  // extern "C"

@@ -5,11 +5,13 @@
 
 1. Data: matrices 0..train+test-1 of the selector set (2D 5-point and 3D
    27-point stencils, FEM-like bands, web-like lognormal rows, dense rows in a
-   sparse matrix; 1e4..2e6 rows), drawn on the GPU.  For each: the 8 features
-   (sss_csr_features) and the median time of every (W, S) class of the grid
-   (sss_csr_spmv_autotune, `reps` timed runs each), plus the time of the
-   default parameters (W = 8, S = 5: the paper's Table 3 choice for double
-   precision on its AMD GPU).
+   sparse matrix; 1e4..2e6 rows), drawn on the GPU, each stored once per value
+   type (FP64, FP32, BF16).  For each sample: the 8 features
+   (sss_csr_features; the last is the bytes per stored value) and the median
+   time of every (W, S) class of the grid (sss_csr_spmv_autotune, `reps` timed
+   runs per trial), plus the time of the default parameters for that type
+   (the paper's Table 3 choices for its AMD GPU: W = 8, S = 5 in double
+   precision; W = 16, S = 2 in single).
 2. Training on the first `train` matrices: features z-scored, soft targets
    q_c ~ exp(-(t_c / t_best - 1) / tau), softmax cross-entropy, full-batch
    Adam -- forward, backward and update all by the library's HIP kernels.
@@ -57,27 +59,39 @@ def time_plan(plan, args, reps: int, trials: int = 5) -> float:
     return float(np.median(ts))
 
 
-def collect(indices, reps: int, default_ws=(8, 5)):
+VALUE_TYPES = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
+               "bf16": (torch.bfloat16, torch.float32)}  # (val, x and y)
+
+
+def collect(indices, reps: int, dtypes=("f64", "f32", "bf16")):
+    """One sample per (matrix, value type); the default plan is the library's
+    per-type default (W = 0, S = 0)."""
     from csrgen.torch_gen import selector_matrix_gpu
-    feats, times, t_def, names, sizes = [], [], [], [], []
+    feats, times, t_def, names, kinds, mats, sizes = [], [], [], [], [], [], []
     t0 = time.time()
     for k, i in enumerate(indices):
         d = selector_matrix_gpu(int(i))
-        rp, col, val, x = d["row_ptr"], d["col"], d["val"], d["x"]
-        y = torch.empty(d["m"], dtype=torch.float64, device="cuda")
-        feats.append(sss.features(rp, d["n"], d["nnz"], torch.float64))
-        t, _ = sss.autotune(rp, col, val, x, y, d["n"], reps)
-        times.append(t)
-        plan = sss.Plan(d["m"], d["n"], d["nnz"], W=default_ws[0], S=default_ws[1])
-        t_def.append(time_plan(plan, (rp, col, val, x, y), reps))
-        plan.close()
-        names.append(d["cls"])
-        sizes.append((d["m"], d["nnz"]))
-        del d, rp, col, val, x, y
+        rp, col = d["row_ptr"], d["col"]
+        for kind in dtypes:
+            vt, xt = VALUE_TYPES[kind]
+            val, x = d["val"].to(vt), d["x"].to(xt)
+            y = torch.empty(d["m"], dtype=xt, device="cuda")
+            feats.append(sss.features(rp, d["n"], d["nnz"], vt))
+            t, _ = sss.autotune(rp, col, val, x, y, d["n"], reps)
+            times.append(t)
+            plan = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt)
+            t_def.append(time_plan(plan, (rp, col, val, x, y), reps))
+            plan.close()
+            names.append(d["cls"])
+            kinds.append(kind)
+            mats.append(int(i))
+            sizes.append((d["m"], d["nnz"]))
+            del val, x, y
+        del d, rp, col
         if (k + 1) % 50 == 0:
             log(f"[selector] {k + 1}/{len(indices)} matrices timed ({time.time() - t0:.0f} s)")
     return (np.array(feats, dtype=np.float32), np.array(times), np.array(t_def), np.array(names),
-            np.array(sizes, dtype=np.int64))
+            np.array(kinds), np.array(mats, dtype=np.int64), np.array(sizes, dtype=np.int64))
 
 
 def soft_targets(times: np.ndarray, tau: float) -> np.ndarray:
@@ -136,17 +150,20 @@ def geomean(a) -> float:
     return float(np.exp(np.log(a).mean()))
 
 
-def evaluate(pred: np.ndarray, times: np.ndarray, t_def: np.ndarray, names: np.ndarray) -> dict:
+def evaluate(pred: np.ndarray, times: np.ndarray, t_def: np.ndarray, names: np.ndarray,
+             kinds: np.ndarray) -> dict:
     t_sel = times[np.arange(len(pred)), pred]
     t_best = times.min(axis=1)
     out = {"n": int(len(pred)), "regret": geomean(t_sel / t_best) - 1.0,
            "gain_vs_default": geomean(t_def / t_sel), "grid_gain_vs_default": geomean(t_def / t_best),
            "accuracy": float((pred == times.argmin(axis=1)).mean()),
-           "worst_ratio": float((t_sel / t_best).max()), "per_class": {}}
-    for c in sorted(set(names.tolist())):
-        k = names == c
-        out["per_class"][c] = {"n": int(k.sum()), "regret": geomean(t_sel[k] / t_best[k]) - 1.0,
-                               "gain_vs_default": geomean(t_def[k] / t_sel[k])}
+           "worst_ratio": float((t_sel / t_best).max()), "per_class": {}, "per_value_type": {}}
+    for key, labels in (("per_class", names), ("per_value_type", kinds)):
+        for c in sorted(set(labels.tolist())):
+            k = labels == c
+            out[key][c] = {"n": int(k.sum()), "regret": geomean(t_sel[k] / t_best[k]) - 1.0,
+                           "gain_vs_default": geomean(t_def[k] / t_sel[k]),
+                           "worst_ratio": float((t_sel[k] / t_best[k]).max())}
     return out
 
 
@@ -159,39 +176,44 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--tau", type=float, default=0.03)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--dtypes", default="f64,f32,bf16", help="value types to time each matrix in")
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     sss.lib()
     n_all = args.train + args.test
-    log(f"[selector] timing {n_all} matrices, {sss.N_CLASSES} classes, {args.reps} runs each")
-    feats, times, t_def, names, sizes = collect(range(n_all), args.reps)
+    dtypes = tuple(args.dtypes.split(","))
+    log(f"[selector] timing {n_all} matrices x {dtypes}, {sss.N_CLASSES} classes, {args.reps} runs per trial")
+    feats, times, t_def, names, kinds, mats, sizes = collect(range(n_all), args.reps, dtypes)
     np.savez(os.path.join(args.out, "dataset.npz"), feats=feats, times=times, t_default=t_def, names=names,
-             sizes=sizes)
-    Xtr, Xte = feats[:args.train], feats[args.train:]
+             kinds=kinds, mats=mats, sizes=sizes)
+    tr, te = mats < args.train, mats >= args.train
+    Xtr, Xte = feats[tr], feats[te]
     mean = Xtr.mean(axis=0)
     std = Xtr.std(axis=0)
     std[std == 0] = 1.0
-    Q = soft_targets(times[:args.train], args.tau)
+    Q = soft_targets(times[tr], args.tau)
     params, hist = train((Xtr - mean) / std, Q, args.steps, args.lr, args.seed)
     log(f"[selector] loss {hist}")
-    res_tr = evaluate(predict(params, (Xtr - mean) / std), times[:args.train], t_def[:args.train],
-                      names[:args.train])
-    res_te = evaluate(predict(params, (Xte - mean) / std), times[args.train:], t_def[args.train:],
-                      names[args.train:])
+    res_tr = evaluate(predict(params, (Xtr - mean) / std), times[tr], t_def[tr], names[tr], kinds[tr])
+    res_te = evaluate(predict(params, (Xte - mean) / std), times[te], t_def[te], names[te], kinds[te])
     classes = [list(sss.class_params(c)) for c in range(sss.N_CLASSES)]
     json.dump({"params": [float(v) for v in params], "feature_mean": [float(v) for v in mean],
                "feature_std": [float(v) for v in std], "classes_WS": classes,
                "features": ["log2(m+1)", "log2(n+1)", "log2(nnz+1)", "log2(1+mean)", "log2(1+var)",
                             "log2(1+max)", "empty_frac", "bytes_per_value"],
-               "trained_on": f"selector matrices 0..{args.train - 1} (seed base 10000), FP64, T=64 B=2",
+               "trained_on": f"selector matrices 0..{args.train - 1} (seed base 10000) as {'/'.join(dtypes)}, "
+                             f"T=64 B=2",
                "command": "python -m paper_1504_06474_amd.selector_train " + " ".join(sys.argv[1:])},
               open(os.path.join(args.out, "selector_params.json"), "w"))
     report = {"train": res_tr, "test": res_te, "loss_history": hist, "args": vars(args),
-              "class_best_counts": np.bincount(times.argmin(axis=1), minlength=12).tolist()}
+              "class_best_counts": {k: np.bincount(times[kinds == k].argmin(axis=1), minlength=12).tolist()
+                                    for k in dtypes}}
     json.dump(report, open(os.path.join(args.out, "selector_report.json"), "w"), indent=1)
     log(f"[selector] test regret {res_te['regret']:.4f} gain {res_te['gain_vs_default']:.3f} "
         f"(grid gain {res_te['grid_gain_vs_default']:.3f}) accuracy {res_te['accuracy']:.3f}")
+    for k, v in res_te["per_value_type"].items():
+        log(f"[selector]   {k}: regret {v['regret']:.4f} gain {v['gain_vs_default']:.3f} worst {v['worst_ratio']:.3f}")
 
 
 if __name__ == "__main__":

@@ -77,6 +77,7 @@ def lib():
         L.sss_class_params.argtypes = [I, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
         L.sss_csr_spmv_autotune.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, FP, ctypes.POINTER(I)]
+        L.sss_csr_spmv_plan_create_grid.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, ctypes.POINTER(P)]
         L.sss_mlp_forward.argtypes = [P, P, I, P, P, P, P]
         L.sss_mlp_backward.argtypes = [P, P, P, P, P, P, I, P, P, P, P]
         L.sss_mlp_adam.argtypes = [P, P, P, P, I, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -97,7 +98,7 @@ def lib():
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
-                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_mlp_forward",
+                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
                   "sss_selector_loaded"):
             getattr(L, f).restype = I
@@ -284,6 +285,19 @@ def autotune(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None):
                                        _ptr(val), _ptr(x), _ptr(y), dt, int(reps), _stream(stream), t,
                                        ctypes.byref(best)), "sss_csr_spmv_autotune")
     return np.array(t[:], dtype=np.float64), best.value
+
+
+def plan_grid(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None) -> "Plan":
+    """A plan with the grid's fastest class for this matrix
+    (sss_csr_spmv_plan_create_grid; y is overwritten while timing)."""
+    h = ctypes.c_void_p()
+    dt = _DTYPES[val.dtype]
+    _check(lib().sss_csr_spmv_plan_create_grid(row_ptr.numel() - 1, int(n), val.numel(), _ptr(row_ptr), _ptr(col),
+                                               _ptr(val), _ptr(x), _ptr(y), dt, int(reps), _stream(stream),
+                                               ctypes.byref(h)), "sss_csr_spmv_plan_create_grid")
+    p = Plan.__new__(Plan)
+    p.m, p.n, p.nnz, p.dt, p._h = row_ptr.numel() - 1, int(n), val.numel(), dt, h
+    return p
 
 
 def mlp_forward(params, X, H1, H2, Z, stream=None):

@@ -48,3 +48,11 @@ def test_host_side_argument_checks():
     bad_s = sss.PlanOpts(sss.MODE_FIXED, 8, 0, 9, 0)  # B = 9 out of range
     assert L.sss_csr_spmv_plan_create(10, 10, 10, None, 0, ctypes.byref(bad_s), None, ctypes.byref(h)) == -1
     assert L.sss_csr_spmv_execute(None, None, None, None, None, None, None) == -1
+    grid = sss.MODE_GRID if hasattr(sss, "MODE_GRID") else 1
+    opts = sss.PlanOpts(grid, 0, 0, 0, 0)  # GRID needs the matrix: its own call
+    assert L.sss_csr_spmv_plan_create(10, 10, 10, None, 0, ctypes.byref(opts), None, ctypes.byref(h)) == -2
+    assert L.sss_csr_spmv_plan_create_grid(10, 10, 10, None, None, None, None, None, 0, 5, None, None) == -1
+    # reps < 1 is rejected before any device call
+    assert L.sss_csr_spmv_plan_create_grid(10, 10, 10, None, None, None, None, None, 0, 0, None,
+                                           ctypes.byref(h)) == -1
+    assert h.value is None

@@ -124,3 +124,47 @@ def test_batched_rejects_bad_descriptors(torch_cuda):
         sss.BatchPlan([(rp, colx[1:], v, xx, y, A.n)])
     with pytest.raises(sss.SSSError):
         sss.BatchPlan([{"row_ptr": rp, "col": col, "val": v, "x": xx, "y": y, "n": A.n, "S": 99}])
+
+
+_FULL = {}
+
+
+def _full_set():
+    """The 512-matrix batched workload (seeds 20000..20511, sum nnz ~2.8e8)
+    with integer values and x in {-3..3}: every row sum is exact in FP64 and
+    in FP32 (|partial| <= 9 * 2e5 < 2^24), so any order of addition gives the
+    oracle's value."""
+    if not _FULL:
+        note("  generating the 512-matrix integer-valued batch")
+        _FULL["mats"] = csrgen.batched_set(512, values="int")
+        note("  oracle on 512 matrices")
+        _FULL["refs"] = [oracle.spmv(A.row_ptr, A.col, A.val, x) for A, x in _FULL["mats"]]
+    return _FULL["mats"], _FULL["refs"]
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_batched_full_size_exact(torch_cuda, kind):
+    """All 512 matrices in the launch configuration the benchmark times (the
+    per-dtype default W, S), eager and then replayed from the captured graph
+    with y clobbered in between: every row of every matrix bit-exact."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    tdt = torch.float64 if kind == "f64" else torch.float32
+    mats, refs = _full_set()
+    dev = to_dev(torch, mats, tdt)
+    plan = sss.BatchPlan(dev, dtype=tdt)
+    note(f"  {kind} batch plan {plan.info()}")
+    plan.execute()
+    torch.cuda.synchronize()
+    for (A, _), d, ref in zip(mats, dev, refs):
+        assert_exact(d[4].double().cpu().numpy(), ref)
+    for d in dev:
+        d[4].fill_(float("nan"))
+    torch.cuda.synchronize()
+    plan.graph_launch()
+    torch.cuda.synchronize()
+    for (A, _), d, ref in zip(mats, dev, refs):
+        assert_exact(d[4].double().cpu().numpy(), ref)
+    plan.close()
+    del dev
+    torch.cuda.empty_cache()

@@ -47,17 +47,21 @@ def _time(torch, plan, args, reps=7):
     return time_plan(plan, args, reps) * 1e-3
 
 
-def test_selector_gain_on_held_out(sel):
-    """Held-out selector matrices (indices 2000.., never trained on)."""
+@pytest.mark.parametrize("kind", ["f64", "f32", "bf16"])
+def test_selector_gain_on_held_out(sel, kind):
+    """Held-out selector matrices (indices 2000.., never trained on), stored
+    as `kind`; the default plan is the library's default for that type."""
     torch, sss = sel
     from csrgen.torch_gen import selector_matrix_gpu
+    from paper_1504_06474_amd.selector_train import VALUE_TYPES
+    vt, xt = VALUE_TYPES[kind]
     gains, regrets = [], []
     for i in range(2000, 2015):
         d = selector_matrix_gpu(i)
-        args = (d["row_ptr"], d["col"], d["val"], d["x"], torch.empty(d["m"], dtype=torch.float64, device="cuda"))
+        args = (d["row_ptr"], d["col"], d["val"].to(vt), d["x"].to(xt), torch.empty(d["m"], dtype=xt, device="cuda"))
         # gain: selected vs default plan, both timed the same way
-        p_sel = sss.Plan(d["m"], d["n"], d["nnz"], mode=sss.MODE_SELECTOR, row_ptr=d["row_ptr"])
-        p_def = sss.Plan(d["m"], d["n"], d["nnz"], W=8, S=5)
+        p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, mode=sss.MODE_SELECTOR, row_ptr=d["row_ptr"])
+        p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt)
         t_sel, t_def = _time(torch, p_sel, args), _time(torch, p_def, args)
         gains.append(t_def / t_sel)
         # regret: the picked class against the best class of one grid timing
@@ -72,3 +76,28 @@ def test_selector_gain_on_held_out(sel):
     note(f"  geomean gain over default {g:.3f}, regret vs grid {r:.4f}")
     assert g > 1.1
     assert r < 0.10
+
+
+def test_grid_plan(sel):
+    """GRID mode: the plan carries a class of the grid, computes y like any
+    other plan, and an m = 0 / nnz = 0 matrix gets a plan without timing."""
+    torch, sss = sel
+    A, x = csrgen.config1()
+    rp, col = torch.from_numpy(A.row_ptr).cuda(), torch.from_numpy(A.col).cuda()
+    v, xx = torch.from_numpy(A.val).cuda(), torch.from_numpy(x).cuda()
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    plan = sss.plan_grid(rp, col, v, xx, y, n=A.n, reps=3)
+    info = plan.info()
+    assert (info["W"], info["S"]) in [sss.class_params(c) for c in range(12)]
+    y.fill_(float("nan"))
+    plan.execute(rp, col, v, xx, y)
+    torch.cuda.synchronize()
+    assert_f64_parity(y.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x),
+                      oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
+    plan.close()
+    rp0 = torch.zeros(6, dtype=torch.int32, device="cuda")
+    e = torch.empty(0, device="cuda")
+    p0 = sss.plan_grid(rp0, e.int(), e.double(), torch.zeros(3, dtype=torch.float64, device="cuda"),
+                       torch.empty(5, dtype=torch.float64, device="cuda"), n=3)
+    assert p0.info()["n_tiles"] == 0
+    p0.close()
