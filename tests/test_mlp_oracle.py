@@ -80,7 +80,11 @@ def test_planted_mistakes_fail_the_difference_check(monkeypatch):
         g[-12 - 64 * 12:-12] = W3[::-1].ravel()
         return g
 
-    for fn in (bad_relu_mask, bad_transpose):
+    def bad_mean(p_, X_, Q_):
+        # mistake: the sum over samples instead of the mean
+        return orig(p_, X_, Q_) * X_.shape[0]
+
+    for fn in (bad_relu_mask, bad_transpose, bad_mean):
         g = fn(p, X, Q)
         worst = 0.0
         for i in range(0, mlp.N_PARAMS, 7):
