@@ -395,6 +395,25 @@ def main():
     s2_ms = float(s2.mean())
     log(f"[bench] stage1 {s1_ms * 1e3:.2f} us, stage2 {s2_ms * 1e3:.2f} us")
 
+    # memory floors of stage 1's access pattern with the same tiling and the
+    # same rotated copies: col/val streamed alone, and streamed with x gathered
+    floor_out = torch.empty(info["n_bunches"] * 64, dtype=torch.float64, device="cuda")
+    floors = {}
+    for name, gather in (("stream_us", False), ("stream_gather_us", True)):
+        for k in range(args.warmup):
+            rp, col, v, xx, y = copies[k % len(copies)]
+            plan.floor_probe(col, v, xx, floor_out, gather)
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            rp, col, v, xx, y = copies[k % len(copies)]
+            ea[k].record()
+            plan.floor_probe(col, v, xx, floor_out, gather)
+            eb[k].record()
+        torch.cuda.synchronize()
+        floors[name] = float(np.mean([ea[k].elapsed_time(eb[k]) for k in range(args.steps)])) * 1e3
+    del floor_out
+    log(f"[bench] floors {floors}")
+
     # warm cache: the same copy every step
     torch.cuda.synchronize()
     ev0.record()
@@ -445,6 +464,10 @@ def main():
             "warm_cache_us_per_step": round(ms_warm * 1e3, 2),
             "warm_cache_GFLOPs": round(2.0 * nnz / (ms_warm * 1e-3) / 1e9, 2),
             "paper_formula_GBps": round(paper_bytes(m, nnz, 8) / (ms_step * 1e-3) / 1e9, 1),
+            "floors": {"stream_us": round(floors["stream_us"], 2),
+                       "stream_GBps": round(12.0 * nnz / (floors["stream_us"] * 1e-6) / 1e9, 1),
+                       "stream_gather_us": round(floors["stream_gather_us"], 2),
+                       "stage1_frac_of_stream_gather_floor": round(floors["stream_gather_us"] / (s1_ms * 1e3), 3)},
             "sampled_rows_within_1e-12": err_ok,
             "sampled_max_rel_err": max_rel,
         },

@@ -217,6 +217,19 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
                           const void *val, const void *x, void *y, sss_dtype dt, int reps, void *stream,
                           float *class_us, int *best_class);
 
+/* Measurement aid, not part of the method: the memory floor of stage 1's
+ * access pattern under plan p's tiling (W, S, B).  Streams col and val once,
+ * tile by tile, with the same loads and the same one-tile-ahead prefetch as
+ * stage 1; with gather != 0 each value is multiplied by x[col] as in the
+ * products, else x is not read.  No row structure is read, nothing is
+ * segmented, and each lane writes one sum: out[b*64 + lane] for thread-bunch
+ * b, so `out` (device, y type of the plan) holds n_bunches*64 elements
+ * (n_bunches from sss_plan_info).  Comparing stage 1's time with this one
+ * separates the method's own work from the cost of reading the matrix and
+ * gathering x.  Same pointer rules as execute; asynchronous on `stream`. */
+int sss_floor_probe(sss_plan p, const int32_t *col, const void *val, const void *x, void *out, int gather,
+                    void *stream);
+
 /* GRID-mode plan (the selector's fallback, and the judge of its regret):
  * runs sss_csr_spmv_autotune on the caller's matrix and returns in *out a
  * plan with the fastest class's (W, S) and the default B.  Arguments as for

@@ -576,6 +576,48 @@ void sss_stage1(MatCtx a) {
   stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane);
 }
 
+// Measurement aid, not part of the method: the memory floor of stage 1's
+// access pattern.  Same tiling, same lane-contiguous col/val loads and the same
+// one-tile-ahead prefetch as stage 1, with no row pass, no segmentation and no
+// partial stores: each lane sums its products (GATHER) or its values plus
+// columns (stream only) and writes one value, so the loads cannot be dropped.
+template <int DT, int W, bool GATHER>
+__global__ __launch_bounds__(256) void sss_floor(MatCtx a, typename VT<DT>::y_t *__restrict__ out) {
+  using val_t = typename VT<DT>::val_t;
+  using x_t = typename VT<DT>::x_t;
+  using prod_t = typename VT<DT>::prod_t;
+  constexpr int WT = W * kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (tb >= a.n_bunches) return;
+  const int32_t *__restrict__ col = a.col;
+  const val_t *__restrict__ val = static_cast<const val_t *>(a.val);
+  const x_t *__restrict__ x = static_cast<const x_t *>(a.x);
+  const int nnz = a.nnz, S = a.S;
+  const int64_t SWT = (int64_t)S * WT;
+  int cc[W];
+  prod_t av[W], xv[W];
+  load_tile<W>(col, val, (int)(tb * SWT), nnz, lane, cc, av);
+#pragma unroll
+  for (int i = 0; i < W; ++i) xv[i] = GATHER ? (prod_t)x[cc[i]] : (prod_t)cc[i];
+  double acc = 0.0;
+  for (int t = 0; t < S; ++t) {
+    const int64_t b64 = tb * SWT + (int64_t)t * WT;
+    if (b64 >= nnz) break;
+    const bool has_next = (t + 1 < S) && (b64 + WT < nnz);
+    int cn[W];
+    prod_t an[W];
+    if (has_next) load_tile<W>(col, val, (int)b64 + WT, nnz, lane, cn, an);
+#pragma unroll
+    for (int i = 0; i < W; ++i) acc += GATHER ? (double)(av[i] * xv[i]) : (double)(av[i] + xv[i]);
+    if (has_next) {
+#pragma unroll
+      for (int i = 0; i < W; ++i) { xv[i] = GATHER ? (prod_t)x[cn[i]] : (prod_t)cn[i]; av[i] = an[i]; }
+    }
+  }
+  out[tb * kWave + lane] = (typename VT<DT>::y_t)acc;
+}
+
 // Many matrices in one persistent launch: the thread-bunches of all matrices
 // form one nnz-balanced index space (bunch_base = prefix of the per-matrix
 // bunch counts); each wavefront strides over it and finds its matrix by the
@@ -993,6 +1035,30 @@ int launch_batch(sss_plan p, hipStream_t stream) {
 std::mutex g_cache_mu;
 std::map<std::tuple<int, int64_t, int64_t, int64_t>, sss_plan> g_cache;
 
+template <int DT, int W>
+int launch_floor(sss_plan p, const MatCtx &a, void *out, int gather, hipStream_t stream) {
+  using y_t = typename VT<DT>::y_t;
+  const int64_t blocks = (p->n_bunches + p->B - 1) / p->B;
+  if (gather)
+    hipLaunchKernelGGL((sss_floor<DT, W, true>), dim3((unsigned)blocks), dim3(p->B * kWave), 0, stream, a,
+                       static_cast<y_t *>(out));
+  else
+    hipLaunchKernelGGL((sss_floor<DT, W, false>), dim3((unsigned)blocks), dim3(p->B * kWave), 0, stream, a,
+                       static_cast<y_t *>(out));
+  SSS_HIP(hipGetLastError());
+  return SSS_OK;
+}
+
+template <int DT>
+int launch_floor_w(sss_plan p, const MatCtx &a, void *out, int gather, hipStream_t stream) {
+  switch (p->W) {
+    case 4: return launch_floor<DT, 4>(p, a, out, gather, stream);
+    case 8: return launch_floor<DT, 8>(p, a, out, gather, stream);
+    case 16: return launch_floor<DT, 16>(p, a, out, gather, stream);
+    default: return SSS_ERR_UNSUPPORTED;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1052,6 +1118,28 @@ int sss_csr_spmv_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, 
   const int rc = check_call(p, row_ptr, col, val, x, y);
   if (rc != SSS_OK || p->m == 0) return rc;
   return launch_stage1(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sss_floor_probe(sss_plan p, const int32_t *col, const void *val, const void *x, void *out, int gather,
+                    void *stream) {
+  if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
+  if (p->m == 0 || p->nnz == 0) return SSS_OK;
+  if (!col || !val || !out || (gather && !x)) return SSS_ERR_INVALID_VALUE;
+  if (misaligned(col) || misaligned(val)) return SSS_ERR_INVALID_VALUE;
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
+  MatCtx a{};
+  a.col = col; a.val = val; a.x = x;
+  a.m = (int32_t)p->m; a.nnz = (int32_t)p->nnz; a.S = p->S; a.W = p->W;
+  a.n_bunches = p->n_bunches; a.n_tiles = p->n_tiles;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  switch (p->dt) {
+    case SSS_F64: return launch_floor_w<SSS_F64>(p, a, out, gather, s);
+    case SSS_F32: return launch_floor_w<SSS_F32>(p, a, out, gather, s);
+    case SSS_BF16: return launch_floor_w<SSS_BF16>(p, a, out, gather, s);
+    default: return SSS_ERR_UNSUPPORTED;
+  }
 }
 
 int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *stream) {

@@ -77,6 +77,7 @@ def lib():
         L.sss_class_params.argtypes = [I, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
         L.sss_csr_spmv_autotune.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, FP, ctypes.POINTER(I)]
+        L.sss_floor_probe.argtypes = [P, P, P, P, P, I, P]
         L.sss_csr_spmv_plan_create_grid.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, ctypes.POINTER(P)]
         L.sss_mlp_forward.argtypes = [P, P, I, P, P, P, P]
         L.sss_mlp_backward.argtypes = [P, P, P, P, P, P, I, P, P, P, P]
@@ -98,7 +99,7 @@ def lib():
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
-                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_mlp_forward",
+                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
                   "sss_selector_loaded"):
             getattr(L, f).restype = I
@@ -198,6 +199,21 @@ class Plan:
         return {"n_tiles": nt, "n_bunches": nb, "dirty_count": nd, "tile_start": tile_start.copy(),
                 "tile_dirty": tile_dirty.copy(), "heads": heads.copy(), "speculator": spec.copy(),
                 "sync_idx": sync_idx.copy(), "sync_val": sync_val.copy()}
+
+    def floor_probe(self, col: torch.Tensor, val: torch.Tensor, x: Optional[torch.Tensor], out: torch.Tensor,
+                    gather: bool = True, stream=None) -> torch.Tensor:
+        """Memory floor of stage 1's access pattern (sss_floor_probe): streams
+        col/val with this plan's tiling, gathering x when `gather`; writes one
+        sum per lane to `out` (n_bunches * 64 elements of the y type)."""
+        if out.numel() < self.info()["n_bunches"] * 64 or out.dtype != _XTYPE[self.dt]:
+            raise ValueError("out must hold n_bunches * 64 elements of the plan's y type")
+        if val.dtype != _VALTYPE[self.dt] or col.numel() < self.nnz or val.numel() < self.nnz:
+            raise ValueError("col/val do not match the plan")
+        if gather and (x is None or x.dtype != _XTYPE[self.dt] or x.numel() < self.n):
+            raise ValueError("x does not match the plan")
+        _check(lib().sss_floor_probe(self._h, _ptr(col), _ptr(val), _ptr(x) if gather else None, _ptr(out),
+                                     1 if gather else 0, _stream(stream)), "sss_floor_probe")
+        return out
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -231,3 +231,22 @@ def test_synchronizer_runs(torch_cuda, k, delta):
     assert_exact(y, oracle.spmv(A.row_ptr, A.col, A.val, x))
     y2, _ = run_plan(torch_cuda, A, x, W=8, S=2)
     assert_exact(y2, oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+@pytest.mark.parametrize("WS", [(8, 5), (4, 1), (16, 3)])
+def test_floor_probe_reads_every_nonzero_once(torch_cuda, WS):
+    """The measurement kernel streams exactly the matrix: on integer-valued
+    data the sum of its per-lane outputs is sum_k val[k] * x[col[k]] (gather)
+    and sum_k (val[k] + col[k]) (stream only), exactly."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1(int_valued=True)
+    plan = sss.Plan(A.m, A.n, A.nnz, W=WS[0], S=WS[1])
+    rp, col, v, xx = to_dev(A, x)
+    out = torch.full((plan.info()["n_bunches"] * 64,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.floor_probe(col, v, xx, out, gather=True)
+    torch.cuda.synchronize()
+    assert float(out.sum()) == float(np.sum(A.val * x[A.col]))
+    plan.floor_probe(col, v, None, out, gather=False)
+    torch.cuda.synchronize()
+    assert float(out.sum()) == float(np.sum(A.val + A.col))
