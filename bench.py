@@ -217,6 +217,18 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
         with torch.cuda.graph(g):
             separate()
         ms_sep_graph = timed(g.replay, max(3, steps // 4))
+        # the batch autotuner's tile schedule (every class timed on this batch)
+        bp_grid, grid_us, grid_best = sss.BatchPlan.grid(dev, dtype=tdt, reps=3)
+        ginfo = bp_grid.info()
+        ms_grid = timed(bp_grid.execute, steps)
+        ms_grid_graph = timed(bp_grid.graph_launch, steps)
+        worst_grid = 0.0
+        for (A, x), d, ref, sc in zip(mats, dev, refs, scales):
+            err = np.abs(d[4].double().cpu().numpy() - ref)
+            nz = sc > 0
+            if nz.any():
+                worst_grid = max(worst_grid, float((err[nz] / sc[nz]).max()))
+        bp_grid.close()
         vb = 8 if kind == "f64" else 4
         byts = sum(alg_bytes(A.m, A.n, A.nnz, vb, vb) for A, _ in mats)
         out[kind] = {"W": info["W"], "S": info["S"], "n_bunches": info["n_bunches"],
@@ -226,7 +238,13 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
                      "speedup_vs_separate_graph": round(ms_sep_graph / ms_batch, 2),
                      "batched_GFLOPs": round(2 * out["sum_nnz"] / (ms_batch * 1e-3) / 1e9, 1),
                      "batched_alg_GBps": round(byts / (ms_batch * 1e-3) / 1e9, 1),
-                     "max_err_scaled_vs_f64_oracle": worst}
+                     "max_err_scaled_vs_f64_oracle": worst,
+                     "autotuned": {"W": ginfo["W"], "S": ginfo["S"], "grid_class_us": [round(float(t), 1) for t in grid_us],
+                                   "batched_us": round(ms_grid * 1e3, 1),
+                                   "batched_graph_us": round(ms_grid_graph * 1e3, 1),
+                                   "speedup_vs_separate": round(ms_sep / ms_grid, 2),
+                                   "speedup_vs_separate_graph": round(ms_sep_graph / ms_grid, 2),
+                                   "max_err_scaled_vs_f64_oracle": worst_grid}}
         log(f"[bench] batched {kind}: {out[kind]}")
         del g, plans, bp, dev
         torch.cuda.synchronize()

@@ -154,6 +154,17 @@ typedef struct {
 int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, const sss_plan_opts *opts,
                           void *stream, sss_plan *out);
 
+/* Batched GRID plan: the autotuner's choice of tile schedule for a batch.
+ * Builds a batch plan for every class (W, S) of the grid, with that S for
+ * every matrix (per-matrix S in `mats` is ignored), times each with the
+ * autotuner's protocol (see sss_csr_spmv_autotune; `reps` runs of the whole
+ * batch per trial) and returns the fastest in *out (NULL on any error).
+ * class_us (host, 12 floats, may be NULL) receives each class's microseconds
+ * per batch launch, *best_class (may be NULL) the chosen class.  Every y is
+ * overwritten.  Allocates and synchronises. */
+int sss_batch_plan_create_grid(int count, const sss_csr_desc *mats, sss_dtype dt, int reps, void *stream,
+                               float *class_us, int *best_class, sss_plan *out);
+
 /* Run a batch plan on `stream`: two launches (stage 1, stage 2), no
  * allocation, no host synchronisation. */
 int sss_batch_execute(sss_plan p, void *stream);

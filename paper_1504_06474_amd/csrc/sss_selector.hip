@@ -188,6 +188,50 @@ struct SelectorState {
 std::mutex g_sel_mu;
 SelectorState g_sel[64];
 
+// The autotuners' timing protocol.  Two warm-up runs of every candidate, then
+// kTrials rounds over the candidates in turn (a clock ramp or any other
+// transient lands on one trial of one candidate, which the median drops);
+// each trial is `reps` back-to-back runs between two events on `s`, i.e. the
+// device's time per run, not the host's launch latency.  med[c] = the median
+// trial's microseconds per run of candidate c.
+template <typename Run>
+int time_interleaved(int n, const Run &run, int reps, hipStream_t s, float *med) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = SSS_OK;
+  if (hipEventCreate(&e0) != hipSuccess) rc = SSS_ERR_HIP;
+  if (rc == SSS_OK && hipEventCreate(&e1) != hipSuccess) rc = SSS_ERR_HIP;
+  for (int c = 0; c < n && rc == SSS_OK; ++c)
+    for (int k = 0; k < 2 && rc == SSS_OK; ++k) rc = run(c);
+  std::vector<std::vector<float>> t((size_t)n);
+  for (int r = 0; r < kTrials && rc == SSS_OK; ++r) {
+    for (int c = 0; c < n && rc == SSS_OK; ++c) {
+      hipError_t e = hipEventRecord(e0, s);
+      for (int k = 0; k < reps && rc == SSS_OK && e == hipSuccess; ++k) rc = run(c);
+      if (rc == SSS_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+      if (rc == SSS_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (rc == SSS_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) { g_sel_hip = e; rc = SSS_ERR_HIP; }
+      t[(size_t)c].push_back(ms * 1000.f / (float)reps);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc != SSS_OK) return rc;
+  for (int c = 0; c < n; ++c) {
+    std::sort(t[(size_t)c].begin(), t[(size_t)c].end());
+    med[c] = t[(size_t)c][t[(size_t)c].size() / 2];
+  }
+  return SSS_OK;
+}
+
+int argmin(const float *v, int n) {
+  int best = 0;
+  for (int c = 1; c < n; ++c)
+    if (v[c] < v[best]) best = c;
+  return best;
+}
+
 }  // namespace
 
 extern "C" {
@@ -325,52 +369,23 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
                           const void *val, const void *x, void *y, sss_dtype dt, int reps, void *stream,
                           float *class_us, int *best_class) {
   if (reps < 1 || !best_class) return SSS_ERR_INVALID_VALUE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   sss_plan plans[kOut] = {};
   int rc = SSS_OK;
   for (int c = 0; c < kOut && rc == SSS_OK; ++c) {
     sss_plan_opts o = {SSS_MODE_FIXED, kClassW[c], kClassS[c], 0, 0};
     rc = sss_csr_spmv_plan_create(m, n, nnz, row_ptr, dt, &o, stream, &plans[c]);
   }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (rc == SSS_OK && hipEventCreate(&e0) != hipSuccess) rc = SSS_ERR_HIP;
-  if (rc == SSS_OK && hipEventCreate(&e1) != hipSuccess) rc = SSS_ERR_HIP;
-  // warm every class, then kTrials rounds over the classes in turn (a clock
-  // ramp or any other transient lands on one trial of one class, which the
-  // median drops); each trial is `reps` back-to-back runs between two events:
-  // the device's time per run, not the host's launch latency
-  for (int c = 0; c < kOut && rc == SSS_OK; ++c)
-    for (int k = 0; k < 2 && rc == SSS_OK; ++k) rc = sss_csr_spmv_execute(plans[c], row_ptr, col, val, x, y, stream);
-  std::vector<std::vector<float>> t(kOut);
-  for (int r = 0; r < kTrials && rc == SSS_OK; ++r) {
-    for (int c = 0; c < kOut && rc == SSS_OK; ++c) {
-      hipError_t e = hipEventRecord(e0, s);
-      for (int k = 0; k < reps && rc == SSS_OK && e == hipSuccess; ++k)
-        rc = sss_csr_spmv_execute(plans[c], row_ptr, col, val, x, y, stream);
-      if (rc == SSS_OK && e == hipSuccess) e = hipEventRecord(e1, s);
-      if (rc == SSS_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (rc == SSS_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) { g_sel_hip = e; rc = SSS_ERR_HIP; }
-      t[c].push_back(ms * 1000.f / (float)reps);
-    }
-  }
+  float med[kOut];
+  if (rc == SSS_OK)
+    rc = time_interleaved(
+        kOut, [&](int c) { return sss_csr_spmv_execute(plans[c], row_ptr, col, val, x, y, stream); }, reps,
+        static_cast<hipStream_t>(stream), med);
   for (int c = 0; c < kOut; ++c) {
     const int drc = sss_plan_destroy(plans[c]);
     if (rc == SSS_OK) rc = drc;
   }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
   if (rc != SSS_OK) return rc;
-  float med[kOut];
-  for (int c = 0; c < kOut; ++c) {
-    std::sort(t[c].begin(), t[c].end());
-    med[c] = t[c][t[c].size() / 2];
-  }
-  int best = 0;
-  for (int c = 1; c < kOut; ++c)
-    if (med[c] < med[best]) best = c;
-  *best_class = best;
+  *best_class = argmin(med, kOut);
   if (class_us) std::memcpy(class_us, med, sizeof(med));
   return SSS_OK;
 }
@@ -389,6 +404,40 @@ int sss_csr_spmv_plan_create_grid(int64_t m, int64_t n, int64_t nnz, const int32
     o.S = kClassS[best];
   }
   return sss_csr_spmv_plan_create(m, n, nnz, row_ptr, dt, &o, stream, out);
+}
+
+int sss_batch_plan_create_grid(int count, const sss_csr_desc *mats, sss_dtype dt, int reps, void *stream,
+                               float *class_us, int *best_class, sss_plan *out) {
+  if (!out || reps < 1 || count < 0 || (count > 0 && !mats)) return SSS_ERR_INVALID_VALUE;
+  *out = nullptr;
+  // every matrix takes the class's S: per-matrix S in the descriptors is
+  // ignored here
+  std::vector<sss_csr_desc> d(mats, mats + count);
+  for (auto &e : d) e.S = 0;
+  sss_plan plans[kOut] = {};
+  int rc = SSS_OK;
+  for (int c = 0; c < kOut && rc == SSS_OK; ++c) {
+    sss_plan_opts o = {SSS_MODE_FIXED, kClassW[c], kClassS[c], 0, 0};
+    rc = sss_batch_plan_create(count, d.data(), dt, &o, stream, &plans[c]);
+  }
+  float med[kOut];
+  if (rc == SSS_OK)
+    rc = time_interleaved(kOut, [&](int c) { return sss_batch_execute(plans[c], stream); }, reps,
+                          static_cast<hipStream_t>(stream), med);
+  const int best = rc == SSS_OK ? argmin(med, kOut) : -1;
+  for (int c = 0; c < kOut; ++c) {
+    if (c == best) continue;
+    const int drc = sss_plan_destroy(plans[c]);
+    if (rc == SSS_OK) rc = drc;
+  }
+  if (rc != SSS_OK) {
+    if (best >= 0) (void)sss_plan_destroy(plans[best]);
+    return rc;
+  }
+  if (class_us) std::memcpy(class_us, med, sizeof(med));
+  if (best_class) *best_class = best;
+  *out = plans[best];
+  return SSS_OK;
 }
 
 const char *sss_selector_last_hip_error(void) { return hipGetErrorString(g_sel_hip); }

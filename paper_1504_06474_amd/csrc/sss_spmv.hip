@@ -630,8 +630,12 @@ struct BatchArgs {
   int32_t S_max;
   int64_t total_bunches;
   int64_t total_chunks;
-  int64_t total_waves;        // stage-2 work items: max(total_bunches, count)
+  int64_t total_waves;        // stage-2 work items: total_chunks + total_bunches + count
 };
+
+// gfx950 (one partition) hands consecutive workgroups to its 8 XCDs in turn,
+// workgroup b to XCD b mod 8, and every XCD has its own L2.
+constexpr int kXcds = 8;
 
 template <int DT, int W>
 __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
@@ -639,8 +643,18 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   uint32_t *lds_wave = lds_words + wid * stage1_lds_words(W, b.S_max);
-  const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid; g < b.total_bunches; g += n_waves) {
+  // XCD-aware split: the workgroups with b mod G = k stride over the k-th
+  // contiguous G-th of the global bunch space.  Each XCD then works through
+  // its own run of matrices, and its L2 holds the x of the few matrices in
+  // its window instead of those of every matrix in flight on the chip.  (The
+  // split is correct for any placement of workgroups; the placement only
+  // decides the speed.)
+  const int G = min((int)gridDim.x, kXcds);
+  const int k = (int)(blockIdx.x % G);
+  const int wpb = blockDim.x / kWave;
+  const int64_t stride = (int64_t)((gridDim.x - k + G - 1) / G) * wpb;  // waves of the workgroups b mod G = k
+  const int64_t hi = b.total_bunches * (k + 1) / G;
+  for (int64_t g = b.total_bunches * k / G + (int64_t)(blockIdx.x / G) * wpb + wid; g < hi; g += stride) {
     const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane);
     const MatCtx a = b.mats[i];
     stage1_bunch<DT, W, false>(a, g - b.bunch_base[i], lds_wave, lane);
@@ -661,24 +675,44 @@ __device__ __forceinline__ void fixup_dirty(const MatCtx &a, const int64_t tb, Y
   const int WT = a.W * kWave;
   const uint32_t dm = a.dirty_mask[tb];
   const int n_dirty = __popc(dm);
+  if (n_dirty == 0) return;
+  // all of the bunch's speculator entries in one load: lane e holds entry e
+  int2 ent_lane = make_int2(0, 0);
+  if (lane < n_dirty) {
+    const int4 s = a.speculator[tb * a.S + lane];
+    ent_lane = make_int2(s.x, s.y);
+  }
   for (int ent = 0; ent < n_dirty; ++ent) {
-    const int4 s = a.speculator[tb * a.S + ent];
-    const int start = s.x, stop = s.y;
+    const int start = __shfl(ent_lane.x, ent, kWave);
+    const int stop = __shfl(ent_lane.y, ent, kWave);
     const int n_slots = min(stop - start - 1, WT - 1);
+    // the first chunk's row bounds and the partials do not depend on each
+    // other: issue both before waiting
+    int r = start + 1 + lane;
+    bool in = r < stop;
+    int p0 = in ? rp[r] : 0, p1 = in ? rp[r + 1] : 0;
     for (int i = lane; i < n_slots; i += kWave) slots[i] = y[start + 1 + i];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // one wavefront owns `slots` and its LDS operations execute in order:
+    // only the compiler must keep the order (no wait for memory); every load
+    // of y above has returned before its value reached LDS, so the stores
+    // below cannot overtake them, and other tiles touch other rows
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     int base = 0;
     for (int rb = start + 1; rb < stop; rb += kWave) {
-      const int r = rb + lane;
-      const bool in = r < stop;
-      const bool ne = in && (rp[r] != rp[r + 1]);
+      if (rb != start + 1) {
+        r = rb + lane;
+        in = r < stop;
+        p0 = in ? rp[r] : 0;
+        p1 = in ? rp[r + 1] : 0;
+      }
+      const bool ne = in && (p0 != p1);
       const uint64_t bal = __ballot(ne);
       const int before = __popcll(bal & ((1ull << lane) - 1ull));
       if (in) y[r] = ne ? slots[min(base + before, max(n_slots - 1, 0))] : (YT)0;
       base += __popcll(bal);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -699,19 +733,36 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
   const int64_t nb = a.n_bunches;
   const int64_t tb = chunk0 + lane;
   const bool valid = tb < nb;
+  // one round of loads: this chunk's entries, the kShortRun entries after it
+  // (lanes 0..kShortRun-1) and the one before it; every look-ahead below is a
+  // lane shuffle.  Entries past the last bunch read as index -1, value 0.
   const int idx = valid ? a.sync_idx[tb] : -1;
-  const bool head = valid && (tb == 0 || a.sync_idx[tb - 1] != idx);
-  const bool is_long = head && (tb + kShortRun < nb) && (a.sync_idx[tb + kShortRun] == idx);
+  const double own_v = valid ? a.sync_val[tb] : 0.0;
+  const int64_t tt = chunk0 + kWave + lane;
+  const bool tail_in = lane < kShortRun && tt < nb;
+  const int tail_i = tail_in ? a.sync_idx[tt] : -1;
+  const double tail_v = tail_in ? a.sync_val[tt] : 0.0;
+  const int before_chunk = chunk0 > 0 ? a.sync_idx[chunk0 - 1] : -1;
+  int idn[kShortRun + 1];  // sync_idx[tb + j]
+  double vv[kShortRun];    // sync_val[tb + j]
+#pragma unroll
+  for (int j = 0; j <= kShortRun; ++j) {
+    const int src = lane + j;
+    const int from_own = __shfl(idx, src & (kWave - 1), kWave);
+    const int from_tail = __shfl(tail_i, (src - kWave) & (kWave - 1), kWave);
+    idn[j] = src < kWave ? from_own : from_tail;
+    if (j < kShortRun) {
+      const double vo = __shfl(own_v, src & (kWave - 1), kWave);
+      const double vt = __shfl(tail_v, (src - kWave) & (kWave - 1), kWave);
+      vv[j] = src < kWave ? vo : vt;
+    }
+  }
+  int prev = __shfl(idx, (lane + kWave - 1) & (kWave - 1), kWave);
+  if (lane == 0) prev = before_chunk;
+  const bool head = valid && (tb == 0 || prev != idx);
+  const bool is_long = head && (tb + kShortRun < nb) && (idn[kShortRun] == idx);
   if (head && !is_long) {
     // sync_idx is non-decreasing: the run is a prefix of the next kShortRun
-    int idn[kShortRun];
-    double vv[kShortRun];
-#pragma unroll
-    for (int j = 0; j < kShortRun; ++j) {
-      const bool in = tb + j < nb;
-      idn[j] = in ? a.sync_idx[tb + j] : -1;
-      vv[j] = in ? a.sync_val[tb + j] : 0.0;
-    }
     double sum = 0.0;
 #pragma unroll
     for (int j = 0; j < kShortRun; ++j)
@@ -749,9 +800,11 @@ __device__ __forceinline__ void fixup_leading(const MatCtx &a, const int64_t fir
   for (int64_t r = first; r < r_first; r += stride) y[r] = (YT)0;
 }
 
-// Stage 2 of one matrix: wavefront w re-arranges bunch w's dirty tiles and
-// settles the carries of bunches 64w..64w+63; all threads share the leading
-// rows.  The three parts write disjoint rows.
+// Stage 2 of one matrix: the first ceil(n_bunches / 64) wavefronts settle the
+// carries of 64 bunches each, the next n_bunches wavefronts re-arrange one
+// bunch's dirty tiles each (separate wavefronts, so the two chains of
+// dependent loads run side by side); all threads share the leading rows.  The
+// three parts write disjoint rows.
 template <typename YT>
 __global__ __launch_bounds__(1024) void sss_fixup(MatCtx a) {
   extern __shared__ unsigned char lds_raw[];
@@ -759,14 +812,16 @@ __global__ __launch_bounds__(1024) void sss_fixup(MatCtx a) {
   const int wid = threadIdx.x / kWave;
   YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
-  if (wave < a.n_bunches) fixup_dirty<YT>(a, wave, slots, lane);
-  if (wave * kWave < a.n_bunches) fixup_carries<YT>(a, wave * kWave, lane);
+  const int64_t n_chunks = (a.n_bunches + kWave - 1) / kWave;
+  if (wave < n_chunks) fixup_carries<YT>(a, wave * kWave, lane);
+  else if (wave < n_chunks + a.n_bunches) fixup_dirty<YT>(a, wave - n_chunks, slots, lane);
   fixup_leading<YT>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
-// Stage 2 of a batch, persistent: work item w re-arranges global bunch w's
-// dirty tiles, settles carry chunk w (64 bunches of one matrix) and zeroes
-// matrix w's leading rows.
+// Stage 2 of a batch, persistent: work items 0..total_chunks-1 settle one carry
+// chunk (64 bunches of one matrix) each, the next total_bunches re-arrange one
+// global bunch's dirty tiles each, the last count zero one matrix's leading
+// rows each.
 template <typename YT>
 __global__ __launch_bounds__(1024) void sss_fixup_batch(BatchArgs b) {
   extern __shared__ unsigned char lds_raw[];
@@ -774,19 +829,18 @@ __global__ __launch_bounds__(1024) void sss_fixup_batch(BatchArgs b) {
   const int wid = threadIdx.x / kWave;
   const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid; w < b.total_waves; w += n_waves) {
-    if (w < b.total_bunches) {
-      const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, w, lane);
-      const MatCtx a = b.mats[i];
-      YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
-      fixup_dirty<YT>(a, w - b.bunch_base[i], slots, lane);
-    }
     if (w < b.total_chunks) {
       const int i = (int)wave_rightmost(b.chunk_base, (int64_t)b.count, w, lane);
       const MatCtx a = b.mats[i];
       fixup_carries<YT>(a, (w - b.chunk_base[i]) * kWave, lane);
-    }
-    if (w < b.count) {
-      const MatCtx a = b.mats[w];
+    } else if (w < b.total_chunks + b.total_bunches) {
+      const int64_t g = w - b.total_chunks;
+      const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane);
+      const MatCtx a = b.mats[i];
+      YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
+      fixup_dirty<YT>(a, g - b.bunch_base[i], slots, lane);
+    } else {
+      const MatCtx a = b.mats[w - b.total_chunks - b.total_bunches];
       fixup_leading<YT>(a, lane, kWave);
     }
   }
@@ -988,10 +1042,11 @@ int launch_stage2(sss_plan p, const int32_t *row_ptr, void *y, hipStream_t strea
   a2.row_ptr = row_ptr; a2.y = y; a2.m = (int32_t)p->m; a2.nnz = (int32_t)p->nnz; a2.S = p->S; a2.W = p->W;
   a2.n_bunches = p->n_bunches; a2.n_tiles = p->n_tiles; a2.dirty_mask = p->dirty_mask;
   a2.speculator = p->speculator; a2.sync_idx = p->sync_idx; a2.sync_val = p->sync_val;
-  // one wavefront per thread-bunch (its dirty tiles), one thread per bunch
-  // (its carry run); the grid covers every bunch
+  // one wavefront per 64 bunches (their carry runs), then one per thread-bunch
+  // (its dirty tiles)
   const int wpb = fixup_waves_per_block(p->W, p->dt);
-  const int64_t blocks2 = std::max<int64_t>(1, (p->n_bunches + wpb - 1) / wpb);
+  const int64_t waves2 = (p->n_bunches + kWave - 1) / kWave + p->n_bunches;
+  const int64_t blocks2 = std::max<int64_t>(1, (waves2 + wpb - 1) / wpb);
   const size_t lds2 = (size_t)wpb * WT * y_size(p->dt);
   if (p->dt == SSS_F64)
     hipLaunchKernelGGL(sss_fixup<double>, dim3((unsigned)blocks2), dim3(wpb * kWave), lds2, stream, a2);
@@ -1268,7 +1323,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   ba.S_max = s_max;
   ba.total_bunches = nb_all;
   ba.total_chunks = cb[(size_t)count];
-  ba.total_waves = std::max<int64_t>(nb_all, count);
+  ba.total_waves = ba.total_chunks + nb_all + count;
   // persistent grids: as many workgroups as stay resident on the device
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -1285,6 +1340,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k2, p->wpb2 * kWave, lds2);
   if (e != hipSuccess) return fail(e);
   p->blocks1 = (int)std::max<int64_t>(1, std::min<int64_t>((nb_all + B - 1) / B, (int64_t)cus * std::max(per_cu1, 1)));
+  if (p->blocks1 > kXcds) p->blocks1 -= p->blocks1 % kXcds;  // the same number of workgroups on every XCD
   p->blocks2 = (int)std::max<int64_t>(
       1, std::min<int64_t>((ba.total_waves + p->wpb2 - 1) / p->wpb2, (int64_t)cus * std::max(per_cu2, 1)));
   *out = p;

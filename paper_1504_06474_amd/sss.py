@@ -78,6 +78,8 @@ def lib():
         L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
         L.sss_csr_spmv_autotune.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, FP, ctypes.POINTER(I)]
         L.sss_floor_probe.argtypes = [P, P, P, P, P, I, P]
+        L.sss_batch_plan_create_grid.argtypes = [I, ctypes.POINTER(CsrDesc), I, I, P, FP, ctypes.POINTER(I),
+                                                 ctypes.POINTER(P)]
         L.sss_csr_spmv_plan_create_grid.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, ctypes.POINTER(P)]
         L.sss_mlp_forward.argtypes = [P, P, I, P, P, P, P]
         L.sss_mlp_backward.argtypes = [P, P, P, P, P, P, I, P, P, P, P]
@@ -99,7 +101,7 @@ def lib():
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
-                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_mlp_forward",
+                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
                   "sss_selector_loaded"):
             getattr(L, f).restype = I
@@ -236,6 +238,30 @@ class BatchPlan:
 
     def __init__(self, mats, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0, stream=None):
         L = lib()
+        descs = self._describe(mats, dtype)
+        opts = PlanOpts(MODE_FIXED, W, S, B, 0)
+        h = ctypes.c_void_p()
+        _check(L.sss_batch_plan_create(len(mats), descs, self.dt, ctypes.byref(opts), _stream(stream),
+                                       ctypes.byref(h)), "sss_batch_plan_create")
+        self._h = h
+
+    @classmethod
+    def grid(cls, mats, dtype=torch.float64, reps: int = 3, stream=None):
+        """The batch plan with the grid autotuner's tile schedule
+        (sss_batch_plan_create_grid); every y is overwritten while timing.
+        Returns (plan, per-class microseconds per batch launch, chosen class)."""
+        L = lib()
+        self = cls.__new__(cls)
+        descs = self._describe(mats, dtype)
+        us = (ctypes.c_float * N_CLASSES)()
+        best = ctypes.c_int()
+        h = ctypes.c_void_p()
+        _check(L.sss_batch_plan_create_grid(len(mats), descs, self.dt, int(reps), _stream(stream), us,
+                                            ctypes.byref(best), ctypes.byref(h)), "sss_batch_plan_create_grid")
+        self._h = h
+        return self, np.array(us[:], dtype=np.float64), best.value
+
+    def _describe(self, mats, dtype):
         self.dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
         descs = (CsrDesc * max(1, len(mats)))()
         self._keep = []
@@ -252,11 +278,7 @@ class BatchPlan:
             d.row_ptr, d.col, d.val, d.x, d.y = _ptr(rp), _ptr(col), _ptr(val), _ptr(x), _ptr(y)
             d.S = int(mt.get("S", 0))
             self._keep.append((rp, col, val, x, y))
-        opts = PlanOpts(MODE_FIXED, W, S, B, 0)
-        h = ctypes.c_void_p()
-        _check(L.sss_batch_plan_create(len(mats), descs, self.dt, ctypes.byref(opts), _stream(stream),
-                                       ctypes.byref(h)), "sss_batch_plan_create")
-        self._h = h
+        return descs
 
     def info(self) -> dict:
         return Plan.info(self)

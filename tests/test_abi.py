@@ -56,3 +56,5 @@ def test_host_side_argument_checks():
     assert L.sss_csr_spmv_plan_create_grid(10, 10, 10, None, None, None, None, None, 0, 0, None,
                                            ctypes.byref(h)) == -1
     assert h.value is None
+    assert L.sss_batch_plan_create_grid(1, None, 0, 3, None, None, None, ctypes.byref(h)) == -1
+    assert L.sss_batch_plan_create_grid(0, None, 0, 0, None, None, None, ctypes.byref(h)) == -1

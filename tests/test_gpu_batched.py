@@ -168,3 +168,28 @@ def test_batched_full_size_exact(torch_cuda, kind):
     plan.close()
     del dev
     torch.cuda.empty_cache()
+
+
+def test_batched_grid_schedule(torch_cuda):
+    """The batch autotuner keeps the fastest class of its own timings, applies
+    that S to every matrix, and its plan computes every y exactly, eager and
+    replayed (integer-valued batch with edge shapes; per-matrix S ignored)."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    mats = batch_set(True)
+    dev = to_dev(torch, mats, torch.float64)
+    descs = [{"row_ptr": d[0], "col": d[1], "val": d[2], "x": d[3], "y": d[4], "n": d[5], "S": 3} for d in dev]
+    plan, us, best = sss.BatchPlan.grid(descs, reps=2)
+    assert us.shape == (12,) and np.all(us > 0)
+    assert best == int(np.argmin(us))
+    info = plan.info()
+    assert (info["W"], info["S"]) == sss.class_params(best)
+    for launch in (plan.execute, plan.graph_launch):
+        for d in dev:
+            d[4].fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        for (A, x), d in zip(mats, dev):
+            assert_exact(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+    plan.close()
