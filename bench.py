@@ -42,7 +42,7 @@ def paper_bytes(m: int, nnz: int, val_size: int) -> int:
     return (m + 1 + nnz) * 4 + (2 * nnz + m) * val_size
 
 
-def measured_traffic(W: int, S: int, B: int):
+def measured_traffic(W: int, S: int, B: int, bind_rows: bool):
     """HBM-side bytes per stage-1 launch from the committed counter record,
     or None when the kernel source or launch shape differs from the one the
     counters were taken on."""
@@ -53,7 +53,8 @@ def measured_traffic(W: int, S: int, B: int):
         src = open(os.path.join(here, "paper_1504_06474_amd", "csrc", "sss_spmv.hip"), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"] or (W, S, B) != (rec["W"], rec["S"], rec["B"]):
+    if (hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"] or (W, S, B) != (rec["W"], rec["S"], rec["B"])
+            or bool(rec.get("bind_rows", False)) != bool(bind_rows)):
         return None
     return int(rec["fetch_kib_raw"] * rec["fetch_factor"] * 1024 + rec["write_kib_raw"] * rec["write_factor"] * 1024)
 
@@ -332,6 +333,8 @@ def main():
     ap.add_argument("--W", type=int, default=0)
     ap.add_argument("--S", type=int, default=0)
     ap.add_argument("--B", type=int, default=0)
+    ap.add_argument("--no-bind-rows", action="store_true",
+                    help="search each thread-bunch's first row in every call instead of once at plan time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["spmv", "copy"], default="spmv")
@@ -367,7 +370,11 @@ def main():
         copies.append((torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
                        torch.from_numpy(A.val).to(dev), torch.from_numpy(x).to(dev),
                        torch.empty(m, dtype=torch.float64, device=dev)))
-    plan = sss.Plan(m, n, nnz, dtype=torch.float64, W=args.W, S=args.S, B=args.B)
+    # plan / analyse (outside the timed region): with bind_rows the tile
+    # boundary search runs once here instead of in every call
+    bind = not args.no_bind_rows
+    plan = sss.Plan(m, n, nnz, dtype=torch.float64, W=args.W, S=args.S, B=args.B, bind_rows=bind,
+                    row_ptr=copies[0][0])
     info = plan.info()
     log(f"[bench] plan {info}")
     torch.cuda.synchronize()
@@ -432,6 +439,23 @@ def main():
     del floor_out
     log(f"[bench] floors {floors}")
 
+    # the other plan variant (first rows searched in every call, or bound)
+    other = sss.Plan(m, n, nnz, dtype=torch.float64, W=args.W, S=args.S, B=args.B, bind_rows=not bind,
+                     row_ptr=copies[0][0])
+    ms_other = time_steps(torch, other, copies, args.steps, args.warmup)
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        rp, col, v, xx, y = copies[k % len(copies)]
+        ea[k].record()
+        other.stage1(rp, col, v, xx, y)
+        eb[k].record()
+        other.stage2(rp, y)
+    torch.cuda.synchronize()
+    s1_other = float(np.mean([ea[k].elapsed_time(eb[k]) for k in range(args.steps)]))
+    other.close()
+    log(f"[bench] {'searching' if bind else 'bound-rows'} plan: {ms_other * 1e3:.2f} us/step, "
+        f"stage1 {s1_other * 1e3:.2f} us")
+
     # warm cache: the same copy every step
     torch.cuda.synchronize()
     ev0.record()
@@ -468,10 +492,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "powerlaw_1M_zipf2_f64", "m": m, "n": n, "nnz": nnz, "W": info["W"],
-                   "S": info["S"], "B": info["B"], "T": 64, "copies_rotated": len(copies)},
+                   "S": info["S"], "B": info["B"], "T": 64, "bind_rows": bind, "copies_rotated": len(copies)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": measured_traffic(info["W"], info["S"], info["B"]),
+                     "traffic": measured_traffic(info["W"], info["S"], info["B"], bind),
                      "kernel": "sss_stage1<f64,W>", "alg_bytes_per_launch": B,
                      "avg_launch_us": round(s1_ms * 1e3, 2)},
         "extras": {
@@ -479,6 +503,8 @@ def main():
             "step_frac_of_peak": round(B / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
             "stage1_us": round(s1_ms * 1e3, 2),
             "stage2_us": round(s2_ms * 1e3, 2),
+            ("searching_plan" if bind else "bound_rows_plan"): {"us_per_step": round(ms_other * 1e3, 2),
+                                                                 "stage1_us": round(s1_other * 1e3, 2)},
             "warm_cache_us_per_step": round(ms_warm * 1e3, 2),
             "warm_cache_GFLOPs": round(2.0 * nnz / (ms_warm * 1e-3) / 1e9, 2),
             "paper_formula_GBps": round(paper_bytes(m, nnz, 8) / (ms_step * 1e-3) / 1e9, 1),

@@ -83,6 +83,11 @@ typedef struct {
   int B;     /* wavefronts per workgroup, 1..4 (0 = default) */
   int debug; /* nonzero: stage 1 also records tile start rows, segment
                 descriptors and dirty flags for sss_plan_debug_dump */
+  int bind_rows; /* nonzero: plan_create runs the tile boundary search of
+                    Section 3.2 once, for every thread-bunch's first row, on
+                    row_ptr (required); execute then reads those rows instead
+                    of searching, and the plan serves only matrices whose
+                    row_ptr has the same contents */
 } sss_plan_opts;
 
 typedef struct sss_plan_s *sss_plan;
@@ -92,8 +97,9 @@ typedef struct sss_plan_s *sss_plan;
  * one entry per thread-bunch, ceil(nnz / (S W T)); the speculator one per
  * tile, ceil(nnz / (W T)), here laid out as S slots per thread-bunch with a
  * per-bunch dirty mask in place of the single global dirty counter.
- * row_ptr (device, may be NULL in FIXED mode) is read only by the GRID and
- * SELECTOR modes, on `stream`, which this call then synchronises.
+ * row_ptr (device, may be NULL in FIXED mode without bind_rows) is read only
+ * by the SELECTOR mode and by bind_rows, on `stream`, which this call then
+ * synchronises.
  * opts may be NULL (FIXED with the defaults).  Returns the plan in *out. */
 int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                              sss_dtype dt, const sss_plan_opts *opts, void *stream,

@@ -347,6 +347,7 @@ struct MatCtx {
   int4 *speculator;      // per bunch, S slots: <start, stop, tile, 0> of its dirty tiles, packed
   int32_t *sync_idx;
   double *sync_val;
+  const int32_t *bunch_row;  // per bunch: its first row, found at plan time (NULL: search)
   int32_t *dbg_start;    // debug plans only
   int32_t *dbg_dirty;
   uint32_t *dbg_heads;
@@ -377,7 +378,8 @@ __device__ __forceinline__ void load_tile(const int32_t *__restrict__ col, const
 }
 
 template <int DT, int W, bool DEBUG>
-__device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, uint32_t *lds_wave, const int lane) {
+__device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, uint32_t *lds_wave, const int lane,
+                                             const int r0_known) {
   using val_t = typename VT<DT>::val_t;
   using x_t = typename VT<DT>::x_t;
   using y_t = typename VT<DT>::y_t;
@@ -405,8 +407,9 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
   prod_t av[W];
   load_tile<W>(col, val, b0, nnz, lane, cc, av);
 
-  // ---- tile boundary search (rightmost match) for the bunch's first row
-  const int r0 = wave_rightmost(rp, m, b0, lane);
+  // ---- tile boundary search (rightmost match) for the bunch's first row,
+  // unless the plan found it once for all calls
+  const int r0 = r0_known >= 0 ? r0_known : wave_rightmost(rp, m, b0, lane);
 
   // ---- descriptor, tile start rows, dirty tiles: one pass over the rows
   for (int i = lane; i < S * WPT; i += kWave) mask[i] = 0u;
@@ -573,7 +576,44 @@ void sss_stage1(MatCtx a) {
   const int wid = threadIdx.x / kWave;
   const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
   if (tb >= a.n_bunches) return;
-  stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane);
+  const int r0 = a.bunch_row ? a.bunch_row[tb] : -1;
+  stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane, r0);
+}
+
+// Plan time: the first row of every thread-bunch, the rightmost match of its
+// first nonzero (Section 3.2's tile boundary search), one thread per bunch.
+__device__ __forceinline__ int32_t rightmost_row(const int32_t *__restrict__ rp, int32_t m, int64_t b) {
+  int32_t lo = 0, hi = m;  // rp[0] = 0 <= b
+  while (lo < hi) {
+    const int32_t mid = lo + (hi - lo + 1) / 2;
+    if ((int64_t)rp[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void sss_bunch_rows(const int32_t *__restrict__ rp, int32_t m, int64_t SWT, int64_t n_bunches,
+                               int32_t *__restrict__ out) {
+  for (int64_t tb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tb < n_bunches;
+       tb += (int64_t)gridDim.x * blockDim.x)
+    out[tb] = rightmost_row(rp, m, tb * SWT);
+}
+
+// Plan time, batches: for global bunch g its matrix (the rightmost i with
+// bunch_base[i] <= g), its first row and its index within the matrix.
+__global__ void sss_batch_bunch_info(const MatCtx *__restrict__ mats, const int64_t *__restrict__ bunch_base,
+                                     int32_t count, int64_t total, int4 *__restrict__ out) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = count;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo + 1) / 2;
+      if (bunch_base[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const MatCtx &a = mats[lo];
+    const int64_t tb = g - bunch_base[lo];
+    out[g] = make_int4(lo, rightmost_row(a.row_ptr, a.m, tb * (int64_t)a.S * a.W * kWave), (int)tb, 0);
+  }
 }
 
 // Measurement aid, not part of the method: the memory floor of stage 1's
@@ -631,6 +671,7 @@ struct BatchArgs {
   int64_t total_bunches;
   int64_t total_chunks;
   int64_t total_waves;        // stage-2 work items: total_chunks + total_bunches + count
+  const int4 *bunch_info;     // per global bunch: <matrix, first row, bunch within the matrix, 0>
 };
 
 // gfx950 (one partition) hands consecutive workgroups to its 8 XCDs in turn,
@@ -655,9 +696,9 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
   const int64_t stride = (int64_t)((gridDim.x - k + G - 1) / G) * wpb;  // waves of the workgroups b mod G = k
   const int64_t hi = b.total_bunches * (k + 1) / G;
   for (int64_t g = b.total_bunches * k / G + (int64_t)(blockIdx.x / G) * wpb + wid; g < hi; g += stride) {
-    const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane);
-    const MatCtx a = b.mats[i];
-    stage1_bunch<DT, W, false>(a, g - b.bunch_base[i], lds_wave, lane);
+    const int4 bi = b.bunch_info[g];
+    const MatCtx a = b.mats[bi.x];
+    stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.y);
   }
 }
 
@@ -935,12 +976,14 @@ struct sss_plan_s {
   int dt = SSS_F64;
   int W = 8, S = 5, B = 2;
   int debug = 0;
+  int bind_rows = 0;
   int64_t n_tiles = 0, n_bunches = 0;
   void *aux = nullptr;
   uint32_t *dirty_mask = nullptr;
   int4 *speculator = nullptr;
   int32_t *sync_idx = nullptr;
   double *sync_val = nullptr;
+  int32_t *bunch_row = nullptr;  // plans made with bind_rows only
   int32_t *dbg_start = nullptr;
   int32_t *dbg_dirty = nullptr;
   uint32_t *dbg_heads = nullptr;
@@ -968,6 +1011,8 @@ int plan_alloc(sss_plan p) {
   const size_t o_spec = off; off = align256(off + sizeof(int4) * (size_t)(nb * p->S + 1));
   const size_t o_sidx = off; off = align256(off + sizeof(int32_t) * (size_t)(nb + 1));
   const size_t o_sval = off; off = align256(off + sizeof(double) * (size_t)(nb + 1));
+  size_t o_br = 0;
+  if (p->bind_rows) { o_br = off; off = align256(off + sizeof(int32_t) * (size_t)(nb + 1)); }
   size_t o_ds = 0, o_dd = 0, o_dh = 0;
   if (p->debug) {
     o_ds = off; off = align256(off + sizeof(int32_t) * (size_t)(nt + 1));
@@ -981,6 +1026,7 @@ int plan_alloc(sss_plan p) {
   p->speculator = reinterpret_cast<int4 *>(base + o_spec);
   p->sync_idx = reinterpret_cast<int32_t *>(base + o_sidx);
   p->sync_val = reinterpret_cast<double *>(base + o_sval);
+  if (p->bind_rows) p->bunch_row = reinterpret_cast<int32_t *>(base + o_br);
   if (p->debug) {
     p->dbg_start = reinterpret_cast<int32_t *>(base + o_ds);
     p->dbg_dirty = reinterpret_cast<int32_t *>(base + o_dd);
@@ -1025,6 +1071,7 @@ int launch_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const 
   a1.m = (int32_t)p->m; a1.nnz = (int32_t)p->nnz; a1.S = p->S; a1.W = p->W; a1.n_bunches = p->n_bunches;
   a1.n_tiles = p->n_tiles;
   a1.dirty_mask = p->dirty_mask; a1.speculator = p->speculator; a1.sync_idx = p->sync_idx; a1.sync_val = p->sync_val;
+  a1.bunch_row = p->bunch_row;
   a1.dbg_start = p->dbg_start; a1.dbg_dirty = p->dbg_dirty; a1.dbg_heads = p->dbg_heads;
   const int64_t blocks1 = (p->n_bunches + p->B - 1) / p->B;
   const size_t lds1 = (size_t)p->B * stage1_lds_words(p->W, p->S) * sizeof(uint32_t);
@@ -1146,12 +1193,25 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
   }
   if (!(W == 4 || W == 8 || W == 16)) return SSS_ERR_UNSUPPORTED;
   if (S < 1 || S > kMaxS || B < 1 || B > 4) return SSS_ERR_INVALID_VALUE;
+  if (o.bind_rows && m > 0 && nnz > 0 && !row_ptr) return SSS_ERR_INVALID_VALUE;
   sss_plan p = new sss_plan_s();
   p->m = m; p->n = n; p->nnz = nnz; p->dt = dt; p->W = W; p->S = S; p->B = B; p->debug = o.debug ? 1 : 0;
+  p->bind_rows = (o.bind_rows && m > 0 && nnz > 0) ? 1 : 0;
   int rc = SSS_OK;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
   if (rc == SSS_OK) rc = plan_alloc(p);
+  if (rc == SSS_OK && p->bind_rows) {
+    // each thread-bunch's first row, once for every later call
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t SWT = (int64_t)p->S * p->W * kWave;
+    const unsigned blocks = (unsigned)std::min<int64_t>((p->n_bunches + 255) / 256, 65535);
+    hipLaunchKernelGGL(sss_bunch_rows, dim3(blocks), dim3(256), 0, s, row_ptr, (int32_t)m, SWT, p->n_bunches,
+                       p->bunch_row);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
+  }
   if (rc != SSS_OK) {
     if (p->aux) (void)hipFree(p->aux);
     delete p;
@@ -1241,7 +1301,6 @@ int sss_plan_destroy(sss_plan p) {
 
 int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, const sss_plan_opts *opts,
                           void *stream, sss_plan *out) {
-  (void)stream;
   if (!out || count < 0 || (count > 0 && !mats)) return SSS_ERR_INVALID_VALUE;
   *out = nullptr;
   if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
@@ -1287,6 +1346,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   const size_t o_sp = off; off = align256(off + sizeof(int4) * (size_t)(spec_all + 1));
   const size_t o_si = off; off = align256(off + sizeof(int32_t) * (size_t)(nb_all + 1));
   const size_t o_sv = off; off = align256(off + sizeof(double) * (size_t)(nb_all + 1));
+  const size_t o_bi = off; off = align256(off + sizeof(int4) * (size_t)(nb_all + 1));
 
   sss_plan p = new sss_plan_s();
   p->batch = true; p->dt = dt; p->W = W; p->S = S; p->B = B;
@@ -1324,6 +1384,19 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   ba.total_bunches = nb_all;
   ba.total_chunks = cb[(size_t)count];
   ba.total_waves = ba.total_chunks + nb_all + count;
+  // every global bunch's matrix, first row and index within the matrix, once
+  // for all calls (the descriptors, and so the row pointers, are bound to the plan)
+  int4 *binfo = reinterpret_cast<int4 *>(base + o_bi);
+  ba.bunch_info = binfo;
+  if (nb_all > 0) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned blocks = (unsigned)std::min<int64_t>((nb_all + 255) / 256, 65535);
+    hipLaunchKernelGGL(sss_batch_bunch_info, dim3(blocks), dim3(256), 0, s, ba.mats, ba.bunch_base, count, nb_all,
+                       binfo);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(e);
+  }
   // persistent grids: as many workgroups as stay resident on the device
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);

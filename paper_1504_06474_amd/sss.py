@@ -49,7 +49,7 @@ class CsrDesc(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int), ("B", ctypes.c_int),
-                ("debug", ctypes.c_int)]
+                ("debug", ctypes.c_int), ("bind_rows", ctypes.c_int)]
 
 
 _lib = None
@@ -135,11 +135,11 @@ class Plan:
 
     def __init__(self, m: int, n: int, nnz: int, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0,
                  debug: bool = False, mode: int = MODE_FIXED, row_ptr: Optional[torch.Tensor] = None,
-                 stream=None):
+                 bind_rows: bool = False, stream=None):
         L = lib()
         self.m, self.n, self.nnz = int(m), int(n), int(nnz)
         self.dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
-        opts = PlanOpts(mode, W, S, B, 1 if debug else 0)
+        opts = PlanOpts(mode, W, S, B, 1 if debug else 0, 1 if bind_rows else 0)
         h = ctypes.c_void_p()
         rc = L.sss_csr_spmv_plan_create(self.m, self.n, self.nnz, _ptr(row_ptr), self.dt, ctypes.byref(opts),
                                         _stream(stream), ctypes.byref(h))

@@ -33,12 +33,13 @@ def _announce(request):
     yield
 
 
-def run_plan(torch, A, x, W=0, S=0, B=0, debug=False, dtype=None):
+def run_plan(torch, A, x, W=0, S=0, B=0, debug=False, dtype=None, bind_rows=False):
     from paper_1504_06474_amd import sss
     dtype = dtype or torch.float64
     xdt = torch.float64 if dtype == torch.float64 else torch.float32
     rp, col, v, xx = to_dev(A, x, val_dtype=dtype, x_dtype=xdt)
-    plan = sss.Plan(A.m, A.n, A.nnz, dtype=dtype, W=W, S=S, B=B, debug=debug)
+    plan = sss.Plan(A.m, A.n, A.nnz, dtype=dtype, W=W, S=S, B=B, debug=debug, bind_rows=bind_rows,
+                    row_ptr=rp if bind_rows else None)
     y = plan.execute(rp, col, v, xx)
     torch.cuda.synchronize()
     return y.double().cpu().numpy(), plan
@@ -250,3 +251,31 @@ def test_floor_probe_reads_every_nonzero_once(torch_cuda, WS):
     plan.floor_probe(col, v, None, out, gather=False)
     torch.cuda.synchronize()
     assert float(out.sum()) == float(np.sum(A.val + A.col))
+
+
+@pytest.mark.parametrize("name", sorted(EDGE) + ["config1"])
+@pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
+def test_bound_rows_plan(torch_cuda, name, WS):
+    """A plan that found every thread-bunch's first row at plan time: the
+    same tile start rows, descriptors, dirty tiles and synchronizer as the
+    searching plan (debug dump), bitwise the same y, exact on integers."""
+    if name == "config1":
+        A, x = csrgen.config1(int_valued=True)
+    else:
+        lengths, n = EDGE[name]
+        A, x = csr_from_lengths(lengths, n, seed=len(lengths))
+    note(f"  {name} m={A.m} nnz={A.nnz} W,S={WS}")
+    y_b, p_b = run_plan(torch_cuda, A, x, W=WS[0], S=WS[1], debug=True, bind_rows=True)
+    y_s, p_s = run_plan(torch_cuda, A, x, W=WS[0], S=WS[1], debug=True)
+    assert_exact(y_b, oracle.spmv(A.row_ptr, A.col, A.val, x))
+    assert np.array_equal(y_b.view(np.int64), y_s.view(np.int64))
+    d_b, d_s = p_b.debug_dump(), p_s.debug_dump()
+    for key in ("tile_start", "tile_dirty", "heads", "sync_idx"):
+        assert np.array_equal(d_b[key], d_s[key]), key
+    assert d_b["dirty_count"] == d_s["dirty_count"]
+
+
+def test_bound_rows_needs_row_ptr(torch_cuda):
+    from paper_1504_06474_amd import sss
+    with pytest.raises(sss.SSSError):
+        sss.Plan(10, 10, 10, bind_rows=True)
