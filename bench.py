@@ -274,8 +274,8 @@ def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
             grid, best = sss.autotune(*args, n=d["n"], reps=5)
             cls = sss.selector_predict(sss.features(d["row_ptr"], d["n"], d["nnz"], vt))
             W, S = sss.class_params(cls)
-            p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt)
-            p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, W=W, S=S)
+            p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, bind_rows=True, row_ptr=d["row_ptr"])
+            p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, W=W, S=S, bind_rows=True, row_ptr=d["row_ptr"])
             t_def, t_sel = t_plan(p_def, args, 5), t_plan(p_sel, args, 5)
             p_def.close()
             p_sel.close()
@@ -299,8 +299,12 @@ def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
     rp, col, v, xx, y, A = bench_matrix
     grid, best = sss.autotune(rp, col, v, xx, y, n=A.n, reps=5)
     cls = sss.selector_predict(sss.features(rp, A.n, A.nnz))
+    p_def = sss.Plan(A.m, A.n, A.nnz, bind_rows=True, row_ptr=rp)
+    t_def = t_plan(p_def, (rp, col, v, xx, y), 5)
+    p_def.close()
     out["benchmark_matrix"] = {"selected": list(sss.class_params(cls)), "selected_us": round(float(grid[cls]), 2),
-                               "grid_best": list(sss.class_params(best)), "grid_best_us": round(float(grid.min()), 2)}
+                               "grid_best": list(sss.class_params(best)), "grid_best_us": round(float(grid.min()), 2),
+                               "default_W8S5_us": round(float(t_def), 2)}
     log(f"[bench] selector: {out}")
     return out
 

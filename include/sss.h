@@ -223,7 +223,8 @@ int sss_class_params(int cls, int *W, int *S);
 int sss_csr_features(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, sss_dtype dt, void *stream,
                      float *feats);
 
-/* Grid autotuner: times y = A x for every class (after two warm-up runs of
+/* Grid autotuner: times y = A x for every class, with plans that bind the
+ * rows (bind_rows) as a plan made for this one matrix would (after two warm-up runs of
  * each class, five rounds over the classes in turn, each a trial of `reps`
  * back-to-back runs between HIP events on `stream`; per class the median
  * trial's mean), writes microseconds per run for each class to HOST
@@ -249,7 +250,8 @@ int sss_floor_probe(sss_plan p, const int32_t *col, const void *val, const void 
 
 /* GRID-mode plan (the selector's fallback, and the judge of its regret):
  * runs sss_csr_spmv_autotune on the caller's matrix and returns in *out a
- * plan with the fastest class's (W, S) and the default B.  Arguments as for
+ * plan with the fastest class's (W, S), the default B and the rows bound
+ * (bind_rows) to this row_ptr.  Arguments as for
  * sss_csr_spmv_autotune; y is overwritten; *out is NULL on any error.
  * Allocates and synchronises (a planning call, not for a timed loop). */
 int sss_csr_spmv_plan_create_grid(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,

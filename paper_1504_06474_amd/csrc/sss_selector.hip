@@ -371,8 +371,10 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
   if (reps < 1 || !best_class) return SSS_ERR_INVALID_VALUE;
   sss_plan plans[kOut] = {};
   int rc = SSS_OK;
+  // the classes are timed as they run for this matrix: rows bound at plan time
+  const int bind = (m > 0 && nnz > 0) ? 1 : 0;
   for (int c = 0; c < kOut && rc == SSS_OK; ++c) {
-    sss_plan_opts o = {SSS_MODE_FIXED, kClassW[c], kClassS[c], 0, 0};
+    sss_plan_opts o = {SSS_MODE_FIXED, kClassW[c], kClassS[c], 0, 0, bind};
     rc = sss_csr_spmv_plan_create(m, n, nnz, row_ptr, dt, &o, stream, &plans[c]);
   }
   float med[kOut];
@@ -395,13 +397,14 @@ int sss_csr_spmv_plan_create_grid(int64_t m, int64_t n, int64_t nnz, const int32
                                   sss_plan *out) {
   if (!out) return SSS_ERR_INVALID_VALUE;
   *out = nullptr;
-  sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
+  sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0, 0};
   if (m > 0 && nnz > 0) {
     int best = 0;
     const int rc = sss_csr_spmv_autotune(m, n, nnz, row_ptr, col, val, x, y, dt, reps, stream, nullptr, &best);
     if (rc != SSS_OK) return rc;
     o.W = kClassW[best];
     o.S = kClassS[best];
+    o.bind_rows = 1;
   }
   return sss_csr_spmv_plan_create(m, n, nnz, row_ptr, dt, &o, stream, out);
 }

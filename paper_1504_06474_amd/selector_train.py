@@ -9,7 +9,8 @@
    type (FP64, FP32, BF16).  For each sample: the 8 features
    (sss_csr_features; the last is the bytes per stored value) and the median
    time of every (W, S) class of the grid (sss_csr_spmv_autotune, `reps` timed
-   runs per trial), plus the time of the default parameters for that type
+   runs per trial, plans with bound rows), plus the time of the default
+   parameters for that type (also with bound rows)
    (the paper's Table 3 choices for its AMD GPU: W = 8, S = 5 in double
    precision; W = 16, S = 2 in single).
 2. Training on the first `train` matrices: features z-scored, soft targets
@@ -79,7 +80,7 @@ def collect(indices, reps: int, dtypes=("f64", "f32", "bf16")):
             feats.append(sss.features(rp, d["n"], d["nnz"], vt))
             t, _ = sss.autotune(rp, col, val, x, y, d["n"], reps)
             times.append(t)
-            plan = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt)
+            plan = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, bind_rows=True, row_ptr=rp)
             t_def.append(time_plan(plan, (rp, col, val, x, y), reps))
             plan.close()
             names.append(d["cls"])

@@ -60,8 +60,9 @@ def test_selector_gain_on_held_out(sel, kind):
         d = selector_matrix_gpu(i)
         args = (d["row_ptr"], d["col"], d["val"].to(vt), d["x"].to(xt), torch.empty(d["m"], dtype=xt, device="cuda"))
         # gain: selected vs default plan, both timed the same way
-        p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, mode=sss.MODE_SELECTOR, row_ptr=d["row_ptr"])
-        p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt)
+        p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, mode=sss.MODE_SELECTOR, row_ptr=d["row_ptr"],
+                         bind_rows=True)
+        p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, bind_rows=True, row_ptr=d["row_ptr"])
         t_sel, t_def = _time(torch, p_sel, args), _time(torch, p_def, args)
         gains.append(t_def / t_sel)
         # regret: the picked class against the best class of one grid timing
