@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--W", type=int, default=0)
     ap.add_argument("--S", type=int, default=0)
     ap.add_argument("--B", type=int, default=0)
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="time only the headline plan (no floor probes, no second plan variant): for profiling runs")
     ap.add_argument("--no-bind-rows", action="store_true",
                     help="search each thread-bunch's first row in every call instead of once at plan time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -427,8 +429,8 @@ def main():
     # memory floors of stage 1's access pattern with the same tiling and the
     # same rotated copies: col/val streamed alone, and streamed with x gathered
     floor_out = torch.empty(info["n_bunches"] * 64, dtype=torch.float64, device="cuda")
-    floors = {}
-    for name, gather in (("stream_us", False), ("stream_gather_us", True)):
+    floors = {"stream_us": float("nan"), "stream_gather_us": float("nan")}
+    for name, gather in (() if args.skip_extras else (("stream_us", False), ("stream_gather_us", True))):
         for k in range(args.warmup):
             rp, col, v, xx, y = copies[k % len(copies)]
             plan.floor_probe(col, v, xx, floor_out, gather)
@@ -444,21 +446,23 @@ def main():
     log(f"[bench] floors {floors}")
 
     # the other plan variant (first rows searched in every call, or bound)
-    other = sss.Plan(m, n, nnz, dtype=torch.float64, W=args.W, S=args.S, B=args.B, bind_rows=not bind,
-                     row_ptr=copies[0][0])
-    ms_other = time_steps(torch, other, copies, args.steps, args.warmup)
-    torch.cuda.synchronize()
-    for k in range(args.steps):
-        rp, col, v, xx, y = copies[k % len(copies)]
-        ea[k].record()
-        other.stage1(rp, col, v, xx, y)
-        eb[k].record()
-        other.stage2(rp, y)
-    torch.cuda.synchronize()
-    s1_other = float(np.mean([ea[k].elapsed_time(eb[k]) for k in range(args.steps)]))
-    other.close()
-    log(f"[bench] {'searching' if bind else 'bound-rows'} plan: {ms_other * 1e3:.2f} us/step, "
-        f"stage1 {s1_other * 1e3:.2f} us")
+    ms_other = s1_other = float("nan")
+    if not args.skip_extras:
+        other = sss.Plan(m, n, nnz, dtype=torch.float64, W=args.W, S=args.S, B=args.B, bind_rows=not bind,
+                         row_ptr=copies[0][0])
+        ms_other = time_steps(torch, other, copies, args.steps, args.warmup)
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            rp, col, v, xx, y = copies[k % len(copies)]
+            ea[k].record()
+            other.stage1(rp, col, v, xx, y)
+            eb[k].record()
+            other.stage2(rp, y)
+        torch.cuda.synchronize()
+        s1_other = float(np.mean([ea[k].elapsed_time(eb[k]) for k in range(args.steps)]))
+        other.close()
+        log(f"[bench] {'searching' if bind else 'bound-rows'} plan: {ms_other * 1e3:.2f} us/step, "
+            f"stage1 {s1_other * 1e3:.2f} us")
 
     # warm cache: the same copy every step
     torch.cuda.synchronize()
@@ -507,12 +511,12 @@ def main():
             "step_frac_of_peak": round(B / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
             "stage1_us": round(s1_ms * 1e3, 2),
             "stage2_us": round(s2_ms * 1e3, 2),
-            ("searching_plan" if bind else "bound_rows_plan"): {"us_per_step": round(ms_other * 1e3, 2),
-                                                                 "stage1_us": round(s1_other * 1e3, 2)},
+            ("searching_plan" if bind else "bound_rows_plan"): None if args.skip_extras else {
+                "us_per_step": round(ms_other * 1e3, 2), "stage1_us": round(s1_other * 1e3, 2)},
             "warm_cache_us_per_step": round(ms_warm * 1e3, 2),
             "warm_cache_GFLOPs": round(2.0 * nnz / (ms_warm * 1e-3) / 1e9, 2),
             "paper_formula_GBps": round(paper_bytes(m, nnz, 8) / (ms_step * 1e-3) / 1e9, 1),
-            "floors": {"stream_us": round(floors["stream_us"], 2),
+            "floors": None if args.skip_extras else {"stream_us": round(floors["stream_us"], 2),
                        "stream_GBps": round(12.0 * nnz / (floors["stream_us"] * 1e-6) / 1e9, 1),
                        "stream_gather_us": round(floors["stream_gather_us"], 2),
                        "stage1_frac_of_stream_gather_floor": round(floors["stream_gather_us"] / (s1_ms * 1e3), 3)},
