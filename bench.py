@@ -44,8 +44,9 @@ def paper_bytes(m: int, nnz: int, val_size: int) -> int:
 
 def measured_traffic(W: int, S: int, B: int, bind_rows: bool):
     """HBM-side bytes per stage-1 launch from the committed counter record,
-    or None when the kernel source or launch shape differs from the one the
-    counters were taken on."""
+    or None when the device code (the kernel source file up to its host
+    side) or the launch shape differs from the one the counters were taken
+    on."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -53,6 +54,7 @@ def measured_traffic(W: int, S: int, B: int, bind_rows: bool):
         src = open(os.path.join(here, "paper_1504_06474_amd", "csrc", "sss_spmv.hip"), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
+    src = src[:src.index(b"struct sss_plan_s {")]  # the device code: every kernel precedes the host side
     if (hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"] or (W, S, B) != (rec["W"], rec["S"], rec["B"])
             or bool(rec.get("bind_rows", False)) != bool(bind_rows)):
         return None
@@ -128,7 +130,7 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                 v = torch.from_numpy(np.ascontiguousarray(vs)).cuda()
             xx = torch.from_numpy(np.ascontiguousarray(xs)).cuda()
             ydt = torch.float64 if kind == "f64" else torch.float32
-            plan = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind])
+            plan = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind], bind_rows=True, row_ptr=rp)
             info = plan.info()
             rec = out.setdefault(kind, {"W": info["W"], "S": info["S"]})
             if values == "uniform":
@@ -140,6 +142,15 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                 vb, xb = sizes[kind]
                 rec.update({"us": round(ms * 1e3, 2), "GFLOPs": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
                             "alg_GBps": round(alg_bytes(A.m, A.n, A.nnz, vb, xb) / (ms * 1e-3) / 1e9, 1)})
+                # the learned selector's plan for the same matrix and value type
+                if sss.load_selector():
+                    sel = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind], mode=sss.MODE_SELECTOR, row_ptr=rp,
+                                   bind_rows=True)
+                    ms_sel = time_steps(torch, sel, copies, steps, warmup)
+                    rec["selected"] = {"W": sel.info()["W"], "S": sel.info()["S"], "us": round(ms_sel * 1e3, 2)}
+                    sel.close()
+                    # the timed output must stay the default plan's
+                    plan.execute(*copies[0])
                 y = copies[0][4]
                 del copies
             else:
@@ -157,6 +168,9 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
             log(f"[bench] precision {values} {kind}: {rec.get('us')} us")
     for kind in ("f32", "bf16"):
         out[kind]["speedup_vs_f64"] = round(out["f64"]["us"] / out[kind]["us"], 3)
+    for kind in ("f64", "f32", "bf16"):
+        if "selected" in out[kind]:
+            out[kind]["selected"]["speedup_vs_f64_default"] = round(out["f64"]["us"] / out[kind]["selected"]["us"], 3)
     return out
 
 
@@ -202,7 +216,7 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
             nz = sc > 0
             if nz.any():
                 worst = max(worst, float((err[nz] / sc[nz]).max()))
-        plans = [sss.Plan(A.m, A.n, A.nnz, dtype=tdt) for A, _ in mats]
+        plans = [sss.Plan(A.m, A.n, A.nnz, dtype=tdt, bind_rows=True, row_ptr=d[0]) for (A, _), d in zip(mats, dev)]
 
         def separate():
             for pl, d in zip(plans, dev):

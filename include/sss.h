@@ -9,8 +9,8 @@
  *
  * The method is the two-stage speculative segmented sum (Section 3): nnz is cut
  * into tiles of W*T nonzeros (T = 64, the wavefront width), each wavefront
- * ("thread-bunch") handles S consecutive tiles, a binary search of row_ptr
- * gives each tile's first row, a segment descriptor built on chip marks row
+ * ("thread-bunch") handles S consecutive tiles, a search of row_ptr
+ * (rightmost match) gives each tile's first row, a segment descriptor built on chip marks row
  * heads, a segmented sum produces compact partial sums that are stored to y at
  * speculated positions, and tiles that contain empty rows are labelled dirty.
  * The second stage -- which the paper runs on a CPU core -- runs here as a
@@ -22,7 +22,8 @@
  *   DEVICE pointers on the current HIP device; the library never frees or
  *   retains them past the call.  col and val must be 16-byte aligned (any
  *   hipMalloc / PyTorch allocation is).  A plan owns its auxiliary device
- *   buffers (synchronizer, dirty counter, speculator) from create to destroy.
+ *   buffers (synchronizer, per-bunch dirty masks, speculator) from create to
+ *   destroy.
  *   y is overwritten (not accumulated into).
  *
  * Streams
@@ -118,19 +119,22 @@ int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col,
  * with no other call on that plan in between).
  * Stage 1, speculative execution (Section 3.2 and the appendix algorithm's
  * first-stage function): writes y at speculated positions, the synchronizer,
- * the dirty counter and the speculator.  Stage 2, checking prediction
+ * the dirty masks and the speculator.  Stage 2, checking prediction
  * (Section 3.2; the appendix's synchronization function plus the
  * re-arrangement): adds the cross-bunch carries, moves the dirty tiles' partial
- * sums to their rows, zeroes leading empty rows, and resets the dirty counter.
+ * sums to their rows and zeroes leading empty rows.  Every buffer stage 1
+ * reads is rewritten by it, so nothing needs resetting between calls.
  * They exist so that a caller can time or overlap the stages. */
 int sss_csr_spmv_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val,
                         const void *x, void *y, void *stream);
 int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *stream);
 
 /* The one-call form of the method in double precision: y = A x with the
- * default parameters.  Keeps an internal plan per (device, m, nnz) that it
- * allocates on first use (so the first call for a new size is not
- * graph-capturable; later calls are). */
+ * default parameters.  Keeps an internal plan per (device, stream, m, n, nnz)
+ * that it allocates on first use (so the first call for a new size on a
+ * stream is not graph-capturable; later calls are) and keeps until the
+ * process ends.  Calls on one stream run in order; calls of the same size on
+ * different streams use different plans and may overlap. */
 int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                  const int32_t *col, const double *val, const double *x, double *y,
                  void *stream);

@@ -1135,7 +1135,7 @@ int launch_batch(sss_plan p, hipStream_t stream) {
 }
 
 std::mutex g_cache_mu;
-std::map<std::tuple<int, int64_t, int64_t, int64_t>, sss_plan> g_cache;
+std::map<std::tuple<int, void *, int64_t, int64_t, int64_t>, sss_plan> g_cache;
 
 template <int DT, int W>
 int launch_floor(sss_plan p, const MatCtx &a, void *out, int gather, hipStream_t stream) {
@@ -1273,7 +1273,7 @@ int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, cons
   sss_plan p = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    auto key = std::make_tuple(dev, m, n, nnz);
+    auto key = std::make_tuple(dev, stream, m, n, nnz);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
       p = it->second;
