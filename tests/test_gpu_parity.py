@@ -279,3 +279,33 @@ def test_bound_rows_needs_row_ptr(torch_cuda):
     from paper_1504_06474_amd import sss
     with pytest.raises(sss.SSSError):
         sss.Plan(10, 10, 10, bind_rows=True)
+
+
+@pytest.mark.parametrize("bind", [False, True])
+def test_execute_captured_in_a_graph(torch_cuda, bind):
+    """execute allocates nothing and syncs nothing, so it can be captured:
+    replay the graph several times with new x (and y clobbered) written by
+    the program's own eager work in between; every replay is exact."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1(int_valued=True)
+    rp, col, v, xx = to_dev(A, x)
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    plan = sss.Plan(A.m, A.n, A.nnz, W=8, S=3, bind_rows=bind, row_ptr=rp if bind else None)
+    plan.execute(rp, col, v, xx, y)  # first call outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(rp, col, v, xx, y)
+    rng = np.random.default_rng(5)
+    for rep in range(4):
+        xh = rng.integers(-3, 4, A.n).astype(np.float64)
+        xx.copy_(torch.from_numpy(xh))
+        y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_exact(y.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, xh))
+        plan.execute(rp, col, v, xx, y)  # eager work between replays
+        torch.cuda.synchronize()
+    del g

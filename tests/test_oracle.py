@@ -145,3 +145,23 @@ def test_abs_spmv_bounds_y():
     A, x = csrgen.config1()
     y = oracle.spmv(A.row_ptr, A.col, A.val, x)
     assert np.all(np.abs(y) <= oracle.abs_spmv(A.row_ptr, A.col, A.val, x) * (1 + 1e-15))
+
+
+def test_abs_spmv_exact_closed_form():
+    """(|A||x|)_i = sum_k |a_ik x_k| exactly (dyadic inputs: every product and
+    partial sum is representable), including a row whose terms cancel: there
+    |y_i| = 0 while (|A||x|)_i = 2, so taking |sum| instead of sum|.| fails."""
+    rng = np.random.default_rng(41)
+    for _ in range(40):
+        m, n = int(rng.integers(1, 12)), int(rng.integers(1, 12))
+        rp, col, val, x = random_tiny(rng, m, n)
+        want = [sum((abs(Fraction(float(val[k])) * Fraction(float(x[col[k]]))) for k in range(rp[i], rp[i + 1])),
+                    Fraction(0)) for i in range(m)]
+        got = oracle.abs_spmv(rp, col, val, x)
+        assert [Fraction(float(v)) for v in got] == want
+    rp = np.array([0, 2], np.int32)
+    col = np.array([0, 1], np.int32)
+    val = np.array([1.0, -1.0])
+    x = np.array([1.0, 1.0])
+    assert oracle.spmv(rp, col, val, x)[0] == 0.0
+    assert oracle.abs_spmv(rp, col, val, x)[0] == 2.0
