@@ -142,6 +142,24 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                 vb, xb = sizes[kind]
                 rec.update({"us": round(ms * 1e3, 2), "GFLOPs": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
                             "alg_GBps": round(alg_bytes(A.m, A.n, A.nnz, vb, xb) / (ms * 1e-3) / 1e9, 1)})
+                # memory floors of this plan's access pattern (see the headline)
+                fo = torch.empty(info["n_bunches"] * 64, dtype=ydt, device="cuda")
+                fl = {}
+                for name, gather in (("stream_us", False), ("stream_gather_us", True)):
+                    for k in range(warmup):
+                        c = copies[k % len(copies)]
+                        plan.floor_probe(c[1], c[2], c[3], fo, gather)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    torch.cuda.synchronize()
+                    e0.record()
+                    for k in range(steps):
+                        c = copies[k % len(copies)]
+                        plan.floor_probe(c[1], c[2], c[3], fo, gather)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    fl[name] = round(e0.elapsed_time(e1) / steps * 1e3, 2)
+                rec["floors"] = fl
+                del fo
                 # the learned selector's plan for the same matrix and value type
                 if sss.load_selector():
                     sel = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind], mode=sss.MODE_SELECTOR, row_ptr=rp,
