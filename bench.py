@@ -106,6 +106,57 @@ def error_stats(y, ref, scale) -> dict:
             "max_rel": float(rel.max()) if rel.size else 0.0, "median_rel": float(np.median(rel)) if rel.size else 0.0}
 
 
+def graph_time_us(torch, fn, copies) -> float:
+    """Device time per call of fn(copy): a run of calls captured once into a
+    graph (enough for ~2 ms of work) and replayed for ~0.3 s, so that the
+    host's per-call launch cost does not hide small kernels."""
+    fn(copies[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    fn(copies[1 % len(copies)])
+    e1.record()
+    torch.cuda.synchronize()
+    approx = max(e0.elapsed_time(e1), 1e-3)  # ms
+    reps = int(max(1, min(64, 2.0 / approx)))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn(copies[0])
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for k in range(reps):
+            fn(copies[k % len(copies)])
+    g.replay()
+    torch.cuda.synchronize()
+    trials = int(max(3, min(200, 300.0 / (approx * reps))))
+    e0.record()
+    for _ in range(trials):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / (trials * reps) * 1e3
+    del g
+    return us
+
+
+def rowwise_comparison(torch, sss, copies, n: int, sss_call) -> dict:
+    """The row-wise comparators (CSR-scalar = 1 lane per row ... CSR-vector =
+    64 lanes) against the speculative plan's call sss_call(copy), all timed
+    the same way (graph_time_us) on the same rotated copies."""
+    t_sss = graph_time_us(torch, sss_call, copies)
+    times = {}
+    for lanes in (1, 2, 4, 8, 16, 32, 64):
+        times[lanes] = graph_time_us(torch, lambda c, L=lanes: sss.csr_rowwise(c[0], c[1], c[2], c[3], c[4], n, L),
+                                     copies)
+    best = min(times, key=times.get)
+    return {"sss_us": round(t_sss, 2), "rowwise_us": {str(k): round(v, 2) for k, v in times.items()},
+            "speedup_vs_csr_scalar": round(times[1] / t_sss, 2), "speedup_vs_csr_vector": round(times[64] / t_sss, 2),
+            "best_rowwise_lanes": best, "speedup_vs_best_rowwise": round(times[best] / t_sss, 2),
+            "timing": "graph replay"}
+
+
 def precision_block(torch, sss, steps: int, warmup: int) -> dict:
     """The 4M-row Zipf-1.8 matrix stored FP64 / FP32 / BF16: time per y = A x
     and the error against the FP64 oracle, for uniform and lognormal values."""
@@ -160,6 +211,9 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                     fl[name] = round(e0.elapsed_time(e1) / steps * 1e3, 2)
                 rec["floors"] = fl
                 del fo
+                if kind == "f64":
+                    rec["vs_rowwise"] = rowwise_comparison(torch, sss, copies, A.n, lambda c: plan.execute(*c))
+                    log(f"[bench] precision f64 row-wise comparators: {rec['vs_rowwise']}")
                 # the learned selector's plan for the same matrix and value type
                 if sss.load_selector():
                     sel = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind], mode=sss.MODE_SELECTOR, row_ptr=rp,
@@ -297,6 +351,7 @@ def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
 
     gm = lambda a: float(np.exp(np.mean(np.log(a))))
     acc = {k: {"ratios": [], "gains": [], "hits": 0, "misses": []} for k in VALUE_TYPES}
+    by_class = {}
     for i in range(2000, 2000 + n_matrices):
         d = selector_matrix_gpu(i)
         for kind, (vt, xt) in VALUE_TYPES.items():
@@ -309,6 +364,9 @@ def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
             p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, bind_rows=True, row_ptr=d["row_ptr"])
             p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, W=W, S=S, bind_rows=True, row_ptr=d["row_ptr"])
             t_def, t_sel = t_plan(p_def, args, 5), t_plan(p_sel, args, 5)
+            if kind == "f64" and i < 2005:  # one matrix of each selector class
+                by_class[d["cls"]] = dict(rowwise_comparison(torch, sss, [args], d["n"], lambda c: p_sel.execute(*c)),
+                                          matrix=d["name"], m=d["m"], nnz=d["nnz"], sss_plan=[W, S])
             p_def.close()
             p_sel.close()
             a["ratios"].append(grid[cls] / grid.min())
@@ -320,7 +378,7 @@ def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
                                     "best_us": round(float(grid.min()), 1)})
             del args
         del d
-    out = {"held_out_matrices": n_matrices}
+    out = {"held_out_matrices": n_matrices, "vs_rowwise_by_class": by_class}
     for kind, a in acc.items():
         out[kind] = {"regret_vs_grid": round(gm(a["ratios"]) - 1, 4), "gain_vs_default": round(gm(a["gains"]), 3),
                      "top1": round(a["hits"] / n_matrices, 3), "worst_ratio": round(float(max(a["ratios"])), 3),
@@ -496,6 +554,12 @@ def main():
         log(f"[bench] {'searching' if bind else 'bound-rows'} plan: {ms_other * 1e3:.2f} us/step, "
             f"stage1 {s1_other * 1e3:.2f} us")
 
+    # the paper's comparison (Section 4.3) on this matrix: row-wise kernels
+    comp_c2 = None
+    if not args.skip_extras:
+        comp_c2 = rowwise_comparison(torch, sss, copies, n, lambda c: plan.execute(*c))
+        log(f"[bench] row-wise comparators: {comp_c2}")
+
     # warm cache: the same copy every step
     torch.cuda.synchronize()
     ev0.record()
@@ -552,6 +616,7 @@ def main():
                        "stream_GBps": round(12.0 * nnz / (floors["stream_us"] * 1e-6) / 1e9, 1),
                        "stream_gather_us": round(floors["stream_gather_us"], 2),
                        "stage1_frac_of_stream_gather_floor": round(floors["stream_gather_us"] / (s1_ms * 1e3), 3)},
+            "vs_rowwise": comp_c2,
             "sampled_rows_within_1e-12": err_ok,
             "sampled_max_rel_err": max_rel,
         },

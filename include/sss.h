@@ -239,6 +239,19 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
                           const void *val, const void *x, void *y, sss_dtype dt, int reps, void *stream,
                           float *class_us, int *best_class);
 
+/* Row-wise comparator, NOT the speculative method: the row-based GPU
+ * kernels the paper measures against (Section 4.3, CSR-scalar and
+ * CSR-vector; Section 2.2 explains their load imbalance on irregular
+ * matrices), written for gfx950.  lanes_per_row = 1 is CSR-scalar (a thread
+ * per row), 64 is CSR-vector (a wavefront per row), powers of two between
+ * give sub-wavefront groups; a row's lanes stride over it and reduce by
+ * shuffles.  Plain sums (double for SSS_F64, float otherwise), no plan, no
+ * allocation; y is overwritten.  Arguments as for execute; dt as for plans.
+ * SSS_ERR_UNSUPPORTED for any other lanes_per_row. */
+int sss_csr_rowwise(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, const void *val,
+                    const void *x, void *y, sss_dtype dt, int lanes_per_row, void *stream);
+const char *sss_rowwise_last_hip_error(void);
+
 /* Measurement aid, not part of the method: the memory floor of stage 1's
  * access pattern under plan p's tiling (W, S, B).  Streams col and val once,
  * tile by tile, with the same loads and the same one-tile-ahead prefetch as

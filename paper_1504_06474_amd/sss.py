@@ -78,6 +78,8 @@ def lib():
         L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
         L.sss_csr_spmv_autotune.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, FP, ctypes.POINTER(I)]
         L.sss_floor_probe.argtypes = [P, P, P, P, P, I, P]
+        L.sss_csr_rowwise.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P]
+        L.sss_rowwise_last_hip_error.restype = ctypes.c_char_p
         L.sss_batch_plan_create_grid.argtypes = [I, ctypes.POINTER(CsrDesc), I, I, P, FP, ctypes.POINTER(I),
                                                  ctypes.POINTER(P)]
         L.sss_csr_spmv_plan_create_grid.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, ctypes.POINTER(P)]
@@ -101,7 +103,7 @@ def lib():
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
-                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_mlp_forward",
+                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
                   "sss_selector_loaded"):
             getattr(L, f).restype = I
@@ -323,6 +325,15 @@ def autotune(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None):
                                        _ptr(val), _ptr(x), _ptr(y), dt, int(reps), _stream(stream), t,
                                        ctypes.byref(best)), "sss_csr_spmv_autotune")
     return np.array(t[:], dtype=np.float64), best.value
+
+
+def csr_rowwise(row_ptr, col, val, x, y, n: int, lanes_per_row: int, stream=None):
+    """Row-wise comparator, not the method (sss_csr_rowwise): 1 lane per row
+    is CSR-scalar, 64 is CSR-vector."""
+    _check(lib().sss_csr_rowwise(row_ptr.numel() - 1, int(n), val.numel(), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                 _ptr(x), _ptr(y), _DTYPES[val.dtype], int(lanes_per_row), _stream(stream)),
+           "sss_csr_rowwise")
+    return y
 
 
 def plan_grid(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None) -> "Plan":

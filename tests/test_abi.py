@@ -58,3 +58,8 @@ def test_host_side_argument_checks():
     assert h.value is None
     assert L.sss_batch_plan_create_grid(1, None, 0, 3, None, None, None, ctypes.byref(h)) == -1
     assert L.sss_batch_plan_create_grid(0, None, 0, 0, None, None, None, ctypes.byref(h)) == -1
+    assert L.sss_csr_rowwise(-1, 1, 0, None, None, None, None, None, 0, 1, None) == -1
+    assert L.sss_csr_rowwise(10, 10, 10, None, None, None, None, None, 0, 3, None) == -2
+    assert L.sss_csr_rowwise(10, 10, 10, None, None, None, None, None, 0, 128, None) == -2
+    assert L.sss_csr_rowwise(0, 0, 0, None, None, None, None, None, 0, 64, None) == 0
+    assert L.sss_csr_rowwise(10, 10, 10, None, None, None, None, None, 0, 64, None) == -1
