@@ -168,6 +168,20 @@ def evaluate(pred: np.ndarray, times: np.ndarray, t_def: np.ndarray, names: np.n
     return out
 
 
+def sweep(times: np.ndarray, names: np.ndarray, kinds: np.ndarray) -> dict:
+    """W and S sweeps (the paper's Section 4.5 studies, per class of matrix):
+    for each value type and matrix class, the geometric mean over matrices of
+    t(W, S) / t(best) for every class of the grid, in class order."""
+    rel = times / times.min(axis=1, keepdims=True)
+    out = {}
+    for k in sorted(set(kinds.tolist())):
+        out[k] = {}
+        for c in sorted(set(names.tolist())):
+            sel = (kinds == k) & (names == c)
+            out[k][c] = [round(float(np.exp(np.log(rel[sel, j]).mean())), 3) for j in range(rel.shape[1])]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--train", type=int, default=2000)
@@ -208,6 +222,7 @@ def main():
                "command": "python -m paper_1504_06474_amd.selector_train " + " ".join(sys.argv[1:])},
               open(os.path.join(args.out, "selector_params.json"), "w"))
     report = {"train": res_tr, "test": res_te, "loss_history": hist, "args": vars(args),
+              "sweep_geomean_t_over_best": sweep(times, names, kinds),
               "class_best_counts": {k: np.bincount(times[kinds == k].argmin(axis=1), minlength=12).tolist()
                                     for k in dtypes}}
     json.dump(report, open(os.path.join(args.out, "selector_report.json"), "w"), indent=1)
