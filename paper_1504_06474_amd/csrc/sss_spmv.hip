@@ -411,6 +411,12 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
   // unless the plan found it once for all calls
   const int r0 = r0_known >= 0 ? r0_known : wave_rightmost(rp, m, b0, lane);
 
+  // ---- x gathers of tile 0: they need only the columns, so they go out
+  // before the row pass and travel with its loads
+  prod_t xv[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) xv[i] = (prod_t)x[cc[i]];
+
   // ---- descriptor, tile start rows, dirty tiles: one pass over the rows
   for (int i = lane; i < S * WPT; i += kWave) mask[i] = 0u;
   if (lane == 0) *dflag = 0u;
@@ -418,6 +424,7 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
 
   const int my_b = (int)min<int64_t>(tb * SWT + (int64_t)min(lane, S) * WT, nnz);
   int my_count = 0;  // lane t <= S: rows r >= r0 with rp[r] <= b_t
+  int my_rp = 0;     // lane t <= S: rp of the last such row (the tile's start row)
   for (int rbase = r0;; rbase += kWave) {
     const int r = rbase + lane;
     const int p = (r <= m) ? rp[r] : INT_MAX;
@@ -430,9 +437,15 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     // with b_t < p <= b_{t+1}
     if (r < m && q == p && p > b0 && p <= bS) atomicOr(dflag, 1u << ((p - b0 - 1) / WT));
     for (int t = 0; t <= S; ++t) {
+      // rows with rp <= b_t are a prefix of the chunk; the last of them
+      // (so far) is the start row of tile t
       const int bt = __shfl(my_b, t, kWave);
-      const uint64_t bal = __ballot(p <= bt);
-      if (lane == t) my_count += __popcll(bal);
+      const int c = __popcll(__ballot(p <= bt));
+      const int p_last_in = __shfl(p, c > 0 ? c - 1 : 0, kWave);
+      if (lane == t) {
+        my_count += c;
+        if (c > 0) my_rp = p_last_in;
+      }
     }
     const int p_last = __shfl(p, kWave - 1, kWave);
     if (!(p_last <= bS && rbase + (kWave - 1) < m)) break;
@@ -440,12 +453,6 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
   __builtin_amdgcn_wave_barrier();
   const uint32_t dirty_bits = *dflag;
   const int my_start = (lane <= S) ? r0 + my_count - 1 : 0;
-  const int my_rp = (lane <= S) ? rp[my_start] : 0;
-
-  // ---- x gathers of tile 0
-  prod_t xv[W];
-#pragma unroll
-  for (int i = 0; i < W; ++i) xv[i] = (prod_t)x[cc[i]];
 
   double transmitter = 0.0;
   double sync_v = 0.0;
