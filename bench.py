@@ -246,6 +246,46 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
     return out
 
 
+def cg_block(torch, sss, iters: int = 300) -> dict:
+    """Iterative-solver use: CG on the 5-point Laplacian of a 1024 x 1024
+    grid, one bound plan reused for every product; the plan's one-off
+    analysis time, the time per iteration and the product's share of it."""
+    import csrgen
+    from paper_1504_06474_amd.cg import cg
+    A = csrgen.laplacian2d_csr(1024)
+    rp, col, v = (torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
+    x_true = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, A.n)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = sss.Plan(A.m, A.n, A.nnz, W=8, S=1, bind_rows=True, row_ptr=rp)
+    t_plan_ms = (time.perf_counter() - t0) * 1e3
+    b = torch.empty_like(x_true)
+    plan.execute(rp, col, v, x_true, b)
+    cg(plan, rp, col, v, b, max_iter=10)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    x, it, hist = cg(plan, rp, col, v, b, rtol=0.0, max_iter=iters, check_every=50)
+    e1.record()
+    torch.cuda.synchronize()
+    it_us = e0.elapsed_time(e1) / it * 1e3
+    y = torch.empty_like(b)
+    spmv_us = graph_time_us(torch, lambda c: plan.execute(*c), [(rp, col, v, x_true, y)])
+    s1_us = graph_time_us(torch, lambda c: plan.stage1(*c), [(rp, col, v, x_true, y)])
+    fo = torch.empty(plan.info()["n_bunches"] * 64, dtype=torch.float64, device="cuda")
+    fl_us = graph_time_us(torch, lambda c: plan.floor_probe(c[1], c[2], c[3], fo, True), [(rp, col, v, x_true, y)])
+    byts = alg_bytes(A.m, A.n, A.nnz, 8, 8)
+    out = {"workload": "laplacian2d_1024", "m": A.m, "nnz": A.nnz, "W": 8, "S": 1, "plan_ms": round(t_plan_ms, 3),
+           "iterations": it, "us_per_iteration": round(it_us, 2), "spmv_us": round(spmv_us, 2),
+           "spmv_alg_GBps": round(byts / (spmv_us * 1e-6) / 1e9, 1), "stage1_us": round(s1_us, 2),
+           "stream_gather_floor_us": round(fl_us, 2),
+           "spmv_share": round(spmv_us / it_us, 3), "rel_residual": hist[-1][1],
+           "rel_error": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true))}
+    plan.close()
+    log(f"[bench] cg: {out}")
+    return out
+
+
 def batched_block(torch, sss, steps: int, warmup: int) -> dict:
     """512 uneven power-law matrices: one batched plan (one persistent launch
     per stage, eager and as a replayed HIP graph) against 512 separate plans
@@ -437,6 +477,7 @@ def main():
     ap.add_argument("--skip-precision", action="store_true", help="skip the FP32/BF16 comparison")
     ap.add_argument("--skip-batched", action="store_true", help="skip the 512-matrix batched comparison")
     ap.add_argument("--skip-selector", action="store_true", help="skip the tile-selector evaluation")
+    ap.add_argument("--skip-cg", action="store_true", help="skip the conjugate-gradient workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -628,6 +669,8 @@ def main():
         out["extras"]["precision"] = precision_block(torch, sss, min(args.steps, 50), min(args.warmup, 5))
     if not args.skip_batched:
         out["extras"]["batched"] = batched_block(torch, sss, min(args.steps, 20), 2)
+    if not args.skip_cg:
+        out["extras"]["cg"] = cg_block(torch, sss)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, x, args.cpu_seconds)

@@ -350,6 +350,25 @@ def stencil2d_csr(N: int, seed: int, values: str = "uniform") -> CSR:
     return _from_coo(N * N, N * N, np.concatenate(rows), np.concatenate(cols), rng, values, f"stencil2d_{N}")
 
 
+def laplacian2d_csr(N: int) -> CSR:
+    """The 5-point Laplacian on an N x N grid with Dirichlet boundaries: 4 on
+    the diagonal, -1 for each grid neighbour (symmetric positive definite)."""
+    idx = np.arange(N * N, dtype=np.int64)
+    i, j = idx // N, idx % N
+    rows, cols, vals = [idx], [idx], [np.full(N * N, 4.0)]
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        ok = (i + di >= 0) & (i + di < N) & (j + dj >= 0) & (j + dj < N)
+        rows.append(idx[ok])
+        cols.append((i[ok] + di) * N + (j[ok] + dj))
+        vals.append(np.full(int(ok.sum()), -1.0))
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((cols, rows))
+    row_ptr = np.zeros(N * N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=N * N), out=row_ptr[1:])
+    return CSR(N * N, N * N, row_ptr.astype(np.int32), cols[order].astype(np.int32), vals[order],
+               f"laplacian2d_{N}")
+
+
 def stencil3d_csr(N: int, seed: int, values: str = "uniform") -> CSR:
     """27-point stencil on an N^3 grid."""
     rng = rng_for(seed)

@@ -54,3 +54,18 @@ def test_selector_classes_small():
         A = csrgen.selector_matrix(i, m_lo=2e3, m_hi=5e3)
         assert A.nnz > 0 and A.row_ptr[-1] == A.nnz
         assert A.col.max() < A.n
+
+
+def test_laplacian2d_structure():
+    """5-point Laplacian: symmetric, 4 on the diagonal, interior rows sum to
+    zero, boundary rows to the number of missing neighbours."""
+    N = 6
+    A = csrgen.laplacian2d_csr(N)
+    dense = np.zeros((A.m, A.n))
+    for i in range(A.m):
+        dense[i, A.col[A.row_ptr[i]:A.row_ptr[i + 1]]] = A.val[A.row_ptr[i]:A.row_ptr[i + 1]]
+    assert np.array_equal(dense, dense.T)
+    assert np.all(np.diag(dense) == 4.0)
+    i, j = np.divmod(np.arange(N * N), N)
+    missing = (i == 0).astype(int) + (i == N - 1) + (j == 0) + (j == N - 1)
+    assert np.array_equal(dense.sum(axis=1), missing.astype(float))
