@@ -72,6 +72,11 @@ typedef enum { SSS_MODE_SELECTOR = 0, SSS_MODE_GRID = 1, SSS_MODE_FIXED = 2 } ss
 /* The parameter grid: class c has W = {4, 8, 16}[c / 4], S = {1, 2, 4, 8}[c % 4]
  * (T = 64 and B = 2).  Section 3.4 / Table 3 choose W and S per processor
  * empirically; here they are chosen per matrix. */
+/* Largest m, n or nnz a plan accepts: 2^31 - 4097.  The kernels index rows
+ * and nonzeros in 32-bit; the margin keeps "a tile boundary plus one tile"
+ * and "a row chunk plus one wavefront" inside int32. */
+#define SSS_MAX_INDEX 2147479551
+
 #define SSS_N_CLASSES 12
 #define SSS_N_FEATURES 8
 #define SSS_MLP_HIDDEN 64
@@ -98,6 +103,7 @@ typedef struct sss_plan_s *sss_plan;
  * one entry per thread-bunch, ceil(nnz / (S W T)); the speculator one per
  * tile, ceil(nnz / (W T)), here laid out as S slots per thread-bunch with a
  * per-bunch dirty mask in place of the single global dirty counter.
+ * m, n and nnz must not exceed SSS_MAX_INDEX (else SSS_ERR_INVALID_VALUE).
  * row_ptr (device, may be NULL in FIXED mode without bind_rows) is read only
  * by the SELECTOR mode and by bind_rows, on `stream`, which this call then
  * synchronises.

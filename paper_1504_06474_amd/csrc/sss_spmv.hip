@@ -1176,7 +1176,8 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
                              const sss_plan_opts *opts, void *stream, sss_plan *out) {
   if (!out) return SSS_ERR_INVALID_VALUE;
   *out = nullptr;
-  if (m < 0 || n < 0 || nnz < 0 || m >= INT_MAX || n >= INT_MAX || nnz >= INT_MAX) return SSS_ERR_INVALID_VALUE;
+  if (m < 0 || n < 0 || nnz < 0 || m > SSS_MAX_INDEX || n > SSS_MAX_INDEX || nnz > SSS_MAX_INDEX)
+    return SSS_ERR_INVALID_VALUE;
   if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
   sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
   if (opts) o = *opts;
@@ -1326,7 +1327,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   int64_t tot_m = 0, tot_n = 0, tot_nnz = 0, tot_tiles = 0;
   for (int i = 0; i < count; ++i) {
     const sss_csr_desc &d = mats[i];
-    if (d.m < 0 || d.n < 0 || d.nnz < 0 || d.m >= INT_MAX || d.n >= INT_MAX || d.nnz >= INT_MAX)
+    if (d.m < 0 || d.n < 0 || d.nnz < 0 || d.m > SSS_MAX_INDEX || d.n > SSS_MAX_INDEX || d.nnz > SSS_MAX_INDEX)
       return SSS_ERR_INVALID_VALUE;
     if (d.m > 0 && (!d.row_ptr || !d.y)) return SSS_ERR_INVALID_VALUE;
     if (d.nnz > 0 && (!d.col || !d.val || !d.x || misaligned(d.col) || misaligned(d.val))) return SSS_ERR_INVALID_VALUE;
