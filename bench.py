@@ -246,6 +246,38 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
     return out
 
 
+def host_stage2_block(torch, sss, plan, copies, A, x, reps: int = 20) -> dict:
+    """The paper's split on this discrete GPU: stage 1 on the device, y and
+    the plan's small arrays to host memory, stage 2 on one host core, y back;
+    against the device stage 2 (the product path).  Wall-clock per call."""
+    import oracle
+    y_pin = torch.empty(A.m, dtype=torch.float64, pin_memory=True)
+    parts = np.zeros((reps, 3))
+    for k in range(reps + 2):
+        rp, col, v, xx, y = copies[k % len(copies)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.stage1(rp, col, v, xx, y)
+        y_pin.copy_(y, non_blocking=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.stage2_host(A.row_ptr, y_pin)
+        t2 = time.perf_counter()
+        y.copy_(y_pin, non_blocking=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if k >= 2:
+            parts[k - 2] = (t1 - t0, t2 - t1, t3 - t2)
+    rows = np.random.default_rng(1).choice(A.m, size=500, replace=False)
+    ref = oracle.spmv_rows(A.row_ptr, A.col, A.val, x, rows)
+    got = copies[(reps + 1) % len(copies)][4].cpu().numpy()[rows]
+    scale = oracle.abs_spmv(A.row_ptr, A.col, A.val, x)[rows]
+    mean = [float(v) for v in parts.mean(axis=0) * 1e6]
+    return {"stage1_and_copy_to_host_us": round(mean[0], 1), "host_stage2_us": round(mean[1], 1),
+            "copy_back_us": round(mean[2], 1), "total_us": round(sum(mean), 1),
+            "sampled_rows_within_1e-12": bool(np.all(np.abs(got - ref) <= 1e-12 * scale))}
+
+
 def cg_block(torch, sss, iters: int = 300) -> dict:
     """Iterative-solver use: CG on the 5-point Laplacian of a 1024 x 1024
     grid, one bound plan reused for every product; the plan's one-off
@@ -601,6 +633,13 @@ def main():
         comp_c2 = rowwise_comparison(torch, sss, copies, n, lambda c: plan.execute(*c))
         log(f"[bench] row-wise comparators: {comp_c2}")
 
+    # the paper's heterogeneous split (stage 2 on a host core) on this part
+    host_s2 = None
+    if not args.skip_extras:
+        host_s2 = host_stage2_block(torch, sss, plan, copies, A, x)
+        host_s2["device_execute_us"] = round(ms_step * 1e3, 2)
+        log(f"[bench] stage 2 on the host: {host_s2}")
+
     # warm cache: the same copy every step
     torch.cuda.synchronize()
     ev0.record()
@@ -658,6 +697,7 @@ def main():
                        "stream_gather_us": round(floors["stream_gather_us"], 2),
                        "stage1_frac_of_stream_gather_floor": round(floors["stream_gather_us"] / (s1_ms * 1e3), 3)},
             "vs_rowwise": comp_c2,
+            "stage2_on_host": host_s2,
             "sampled_rows_within_1e-12": err_ok,
             "sampled_max_rel_err": max_rel,
         },

@@ -135,6 +135,16 @@ int sss_csr_spmv_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, 
                         const void *x, void *y, void *stream);
 int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *stream);
 
+/* Stage 2 on a host core, as the paper runs it on its heterogeneous
+ * processors (Section 3.2, Section 3.4), for comparison with the device
+ * fixup: waits for the device, copies the plan's synchronizer, dirty masks
+ * and speculator to host memory, then performs the carries, the dirty-tile
+ * re-arrangement and the zeroing of leading empty rows in one host thread.
+ * row_ptr and y are HOST pointers (y holds stage 1's output, e.g. pinned
+ * host memory that stage 1 wrote directly).  Not for performance: the
+ * device stage 2 is the product path. */
+int sss_csr_spmv_stage2_host(sss_plan p, const int32_t *row_ptr, void *y);
+
 /* The one-call form of the method in double precision: y = A x with the
  * default parameters.  Keeps an internal plan per (device, stream, m, n, nnz)
  * that it allocates on first use (so the first call for a new size on a

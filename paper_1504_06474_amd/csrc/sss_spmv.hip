@@ -1168,6 +1168,44 @@ int launch_floor_w(sss_plan p, const MatCtx &a, void *out, int gather, hipStream
   }
 }
 
+// Stage 2 on a host core, as the paper runs it (Section 3.2, Section 3.4): the
+// same three parts as the device kernel, on host arrays, one thread.
+template <typename YT>
+void stage2_host(sss_plan p, const int32_t *rp, YT *y, const uint32_t *dm, const int4 *spec, const int32_t *si,
+                 const double *sv) {
+  const int64_t nb = p->n_bunches;
+  const int64_t WT = (int64_t)p->W * kWave, SWT = (int64_t)p->S * WT;
+  // leading empty rows
+  const int64_t r_first = nb > 0 ? si[0] : p->m;
+  for (int64_t r = 0; r < r_first; ++r) y[r] = (YT)0;
+  // dirty tiles: partial k >= 1 to the k-th non-empty row strictly inside
+  std::vector<YT> slots((size_t)WT);
+  for (int64_t tb = 0; tb < nb; ++tb) {
+    const int n_dirty = __builtin_popcount(dm[tb]);
+    for (int e = 0; e < n_dirty; ++e) {
+      const int4 s = spec[tb * p->S + e];
+      const int start = s.x, stop = s.y;
+      const int64_t n_slots = std::min<int64_t>((int64_t)stop - start - 1, WT - 1);
+      for (int64_t i = 0; i < n_slots; ++i) slots[(size_t)i] = y[start + 1 + i];
+      int64_t k = 0;
+      for (int64_t r = start + 1; r < stop; ++r) {
+        if (rp[r] != rp[r + 1]) y[r] = slots[(size_t)std::min<int64_t>(k++, std::max<int64_t>(n_slots - 1, 0))];
+        else y[r] = (YT)0;
+      }
+    }
+  }
+  // carries: runs of bunches that begin in the same row, summed in bunch order
+  for (int64_t tb = 0; tb < nb;) {
+    const int idx = si[tb];
+    int64_t e = tb;
+    double sum = 0.0;
+    while (e < nb && si[e] == idx) sum += sv[e++];
+    const bool fresh = (int64_t)rp[idx] == tb * SWT;
+    y[idx] = fresh ? (YT)sum : (YT)((double)y[idx] + sum);
+    tb = e;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1292,6 +1330,25 @@ int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, cons
     }
   }
   return launch(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sss_csr_spmv_stage2_host(sss_plan p, const int32_t *row_ptr, void *y) {
+  if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
+  if (p->m == 0 || p->nnz == 0) return SSS_OK;
+  if (!row_ptr || !y) return SSS_ERR_INVALID_VALUE;
+  const size_t nb = (size_t)p->n_bunches;
+  std::vector<uint32_t> dm(nb);
+  std::vector<int4> spec(nb * (size_t)p->S);
+  std::vector<int32_t> si(nb);
+  std::vector<double> sv(nb);
+  SSS_HIP(hipDeviceSynchronize());
+  SSS_HIP(hipMemcpy(dm.data(), p->dirty_mask, nb * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  SSS_HIP(hipMemcpy(spec.data(), p->speculator, spec.size() * sizeof(int4), hipMemcpyDeviceToHost));
+  SSS_HIP(hipMemcpy(si.data(), p->sync_idx, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+  SSS_HIP(hipMemcpy(sv.data(), p->sync_val, nb * sizeof(double), hipMemcpyDeviceToHost));
+  if (p->dt == SSS_F64) stage2_host(p, row_ptr, static_cast<double *>(y), dm.data(), spec.data(), si.data(), sv.data());
+  else stage2_host(p, row_ptr, static_cast<float *>(y), dm.data(), spec.data(), si.data(), sv.data());
+  return SSS_OK;
 }
 
 int sss_plan_destroy(sss_plan p) {

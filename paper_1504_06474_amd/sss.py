@@ -78,6 +78,7 @@ def lib():
         L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
         L.sss_csr_spmv_autotune.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, FP, ctypes.POINTER(I)]
         L.sss_floor_probe.argtypes = [P, P, P, P, P, I, P]
+        L.sss_csr_spmv_stage2_host.argtypes = [P, P, P]
         L.sss_csr_rowwise.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P]
         L.sss_rowwise_last_hip_error.restype = ctypes.c_char_p
         L.sss_batch_plan_create_grid.argtypes = [I, ctypes.POINTER(CsrDesc), I, I, P, FP, ctypes.POINTER(I),
@@ -103,7 +104,7 @@ def lib():
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
-                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_mlp_forward",
+                  "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_csr_spmv_stage2_host", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
                   "sss_selector_loaded"):
             getattr(L, f).restype = I
@@ -203,6 +204,24 @@ class Plan:
         return {"n_tiles": nt, "n_bunches": nb, "dirty_count": nd, "tile_start": tile_start.copy(),
                 "tile_dirty": tile_dirty.copy(), "heads": heads.copy(), "speculator": spec.copy(),
                 "sync_idx": sync_idx.copy(), "sync_val": sync_val.copy()}
+
+    def stage2_host(self, row_ptr: np.ndarray, y) -> None:
+        """Stage 2 on a host core (sss_csr_spmv_stage2_host), for comparison
+        with the device stage 2: row_ptr a host int32 array, y a host array
+        (numpy or CPU tensor) of the plan's y type holding stage 1's output."""
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        if row_ptr.shape[0] != self.m + 1:
+            raise ValueError("row_ptr must hold m + 1 entries")
+        if isinstance(y, torch.Tensor):
+            if y.device.type != "cpu" or not y.is_contiguous() or y.dtype != _XTYPE[self.dt] or y.numel() < self.m:
+                raise ValueError("y must be a contiguous host tensor of the plan's y type")
+            yp = y.data_ptr()
+        else:
+            if y.dtype != np.dtype(str(_XTYPE[self.dt]).replace("torch.", "")) or not y.flags.c_contiguous or \
+                    y.shape[0] < self.m:
+                raise ValueError("y must be a contiguous host array of the plan's y type")
+            yp = y.ctypes.data
+        _check(lib().sss_csr_spmv_stage2_host(self._h, row_ptr.ctypes.data, yp), "sss_csr_spmv_stage2_host")
 
     def floor_probe(self, col: torch.Tensor, val: torch.Tensor, x: Optional[torch.Tensor], out: torch.Tensor,
                     gather: bool = True, stream=None) -> torch.Tensor:

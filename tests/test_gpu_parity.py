@@ -309,3 +309,26 @@ def test_execute_captured_in_a_graph(torch_cuda, bind):
         plan.execute(rp, col, v, xx, y)  # eager work between replays
         torch.cuda.synchronize()
     del g
+
+
+@pytest.mark.parametrize("name", ["config1", "leading_trailing_empty", "long_row_many_bunches",
+                                  "empty_run_100k_inside_tile", "rows_of_two_tiles_with_empties"])
+@pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
+def test_stage2_on_host(torch_cuda, name, WS):
+    """The paper's split (stage 1 on the GPU, stage 2 on a host core) gives
+    the same exact result on integer-valued inputs."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    if name == "config1":
+        A, x = csrgen.config1(int_valued=True)
+    else:
+        lengths, n = EDGE[name]
+        A, x = csr_from_lengths(lengths, n, seed=len(lengths))
+    rp, col, v, xx = to_dev(A, x)
+    y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+    plan = sss.Plan(A.m, A.n, A.nnz, W=WS[0], S=WS[1])
+    plan.stage1(rp, col, v, xx, y)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy().copy()
+    plan.stage2_host(A.row_ptr, yh)
+    assert_exact(yh, oracle.spmv(A.row_ptr, A.col, A.val, x))
