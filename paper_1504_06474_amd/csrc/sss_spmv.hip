@@ -473,10 +473,6 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     int cn[W];
     prod_t an[W];
     if (has_next) load_tile<W>(col, val, b + WT, nnz, lane, cn, an);
-    prod_t v[W];
-#pragma unroll
-    for (int i = 0; i < W; ++i) v[i] = av[i] * xv[i];
-
     // ---- this lane's W descriptor bits; the tile's first bit is forced
     uint32_t hb = (mask[t * WPT + ((lane * W) >> 5)] >> ((lane * W) & 31)) & LOW;
     const bool bit0 = __builtin_amdgcn_readlane((int)hb, 0) & 1;
@@ -494,14 +490,38 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
       }
     }
 
-    // ---- per-lane segmented reduction: the open (last) segment of the lane
-    Acc<DT> run;
+    // ---- exclusive scan of head counts: the compact index of every partial
+    // (integers only, so it does not wait for the products)
+    const int c_heads = __popc(hb);
+    const int incl = wave_iscan(c_heads);
+    const int cnt = __builtin_amdgcn_readlane(incl, kWave - 1);
+    const int rank0 = incl - c_heads;  // segments closed before this lane's first head
+
+    // ---- one pass over the lane's products.  `pre` = the entries before the
+    // lane's first head (they continue a segment opened in an earlier lane);
+    // every later head closes a segment that lies wholly in this lane, whose
+    // partial goes to its LDS slot at once; `run` = the entries after the
+    // last head (a segment still open at the lane's end).
+    Acc<DT> pre, run;
+    pre.zero();
     run.zero();
-    int f = 0;
+    bool seen = false;
+    int q = rank0;  // slot of the segment that the lane's next head closes, plus one
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      if ((hb >> i) & 1u) { f = 1; run.zero(); }
-      run.add(v[i]);
+      const prod_t pi = av[i] * xv[i];
+      if ((hb >> i) & 1u) {
+        if (seen) {
+          double pv = run.value();
+          if (q == 1) pv += tx;
+          part[q - 1] = pv;
+        }
+        seen = true;
+        ++q;
+        run.zero();
+      }
+      if (seen) run.add(pi);
+      else pre.add(pi);
     }
     // ---- the next tile's x gathers go out while this tile finishes
     if (has_next) {
@@ -509,34 +529,25 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
       for (int i = 0; i < W; ++i) { xv[i] = (prod_t)x[cn[i]]; av[i] = an[i]; }
     }
     // ---- wave segmented scan of the open segments; carry into each lane
-    Acc<DT> inc = run;
+    Acc<DT> inc = seen ? run : pre;
+    int f = seen ? 1 : 0;
     wave_seg_scan(inc, f);
     const Acc<DT> carry = dpp_acc<kWaveShr1, 0xf>(inc);
 
-    // ---- exclusive scan of head counts: compact rank of each partial
-    const int c_heads = __popc(hb);
-    const int incl = wave_iscan(c_heads);
-    const int cnt = __builtin_amdgcn_readlane(incl, kWave - 1);
-    int rank = incl - c_heads;
-
-    // ---- partial of segment q (completed at head q+1, or at the tile end)
-    // into LDS slot q
-    Acc<DT> cur = carry;
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      if ((hb >> i) & 1u) {
-        if (rank > 0) {
-          double pv = cur.value();
-          if (rank == 1) pv += tx;
-          part[rank - 1] = pv;
-        }
-        ++rank;
-        cur.zero();
-      }
-      cur.add(v[i]);
+    // ---- the segment closed by this lane's first head: carry + pre; the
+    // segment open at the tile's end (last lane): its run, or carry + pre
+    // when the last lane holds no head
+    if (seen && rank0 > 0) {
+      Acc<DT> c = pre;
+      c.prepend(carry);
+      double pv = c.value();
+      if (rank0 == 1) pv += tx;
+      part[rank0 - 1] = pv;
     }
     if (lane == kWave - 1) {
-      double pv = cur.value();
+      Acc<DT> c = pre;
+      c.prepend(carry);
+      double pv = seen ? run.value() : c.value();
       if (cnt == 1) pv += tx;
       part[cnt - 1] = pv;
     }
