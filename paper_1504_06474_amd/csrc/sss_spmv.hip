@@ -583,10 +583,19 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
 }
 
 
+// Occupancy asked of the register allocator per instance: the most waves per
+// SIMD each instance reaches without spilling (hipcc's resource report; any
+// higher target spills).  Only FP64 with W = 4 gains from asking (6 instead
+// of 5); the others already run at their spill-free maximum.
+template <int DT, int W>
+constexpr int stage1_waves_per_eu() { return (DT == SSS_F64 && W == 4) ? 6 : 1; }
+
 template <int DT, int W, bool DEBUG>
 __global__ __launch_bounds__(256)
 #if SSS_WAVES_PER_EU
 __attribute__((amdgpu_waves_per_eu(SSS_WAVES_PER_EU, 8)))
+#else
+__attribute__((amdgpu_waves_per_eu(stage1_waves_per_eu<DT, W>(), 8)))
 #endif
 void sss_stage1(MatCtx a) {
   extern __shared__ uint32_t lds_words[];
