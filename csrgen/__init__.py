@@ -11,7 +11,7 @@ matrices with irregular power-law ones whose longest rows hold O(n) entries):
                           forced empty (the empty-row case of Section 3.2).
 * ``powerlaw_csr``     -- Zipf / Zipf-Mandelbrot row lengths (irregular family).
 * ``stencil2d_csr`` / ``stencil3d_csr`` / ``fem_band_csr`` / ``weblike_csr`` /
-  ``dense_rows_csr``  -- the classes used to train and judge the tile selector.
+  ``dense_rows_csr``  -- the classes used to train and evaluate the tile selector.
 * ``batched_set``      -- many uneven power-law matrices for the batched path.
 
 Column indices are unique and sorted within each row; values and ``x`` are

@@ -281,7 +281,7 @@ const char *sss_rowwise_last_hip_error(void);
 int sss_floor_probe(sss_plan p, const int32_t *col, const void *val, const void *x, void *out, int gather,
                     void *stream);
 
-/* GRID-mode plan (the selector's fallback, and the judge of its regret):
+/* GRID-mode plan (the selector's fallback, and the yardstick of its regret):
  * runs sss_csr_spmv_autotune on the caller's matrix and returns in *out a
  * plan with the fastest class's (W, S), the default B and the rows bound
  * (bind_rows) to this row_ptr.  Arguments as for

@@ -142,6 +142,8 @@ class Plan:
         L = lib()
         self.m, self.n, self.nnz = int(m), int(n), int(nnz)
         self.dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+        if mode == MODE_SELECTOR and not L.sss_selector_loaded():
+            load_selector()  # the network shipped with the package, once per device
         opts = PlanOpts(mode, W, S, B, 1 if debug else 0, 1 if bind_rows else 0)
         h = ctypes.c_void_p()
         rc = L.sss_csr_spmv_plan_create(self.m, self.n, self.nnz, _ptr(row_ptr), self.dt, ctypes.byref(opts),
