@@ -221,6 +221,7 @@ int sss_plan_debug_size(sss_plan p, size_t *bytes);
  *   int32 tile_dirty[n_tiles]          (debug plans only, else zeros)
  *   uint32 heads[n_tiles * words_per_tile]  segment descriptor bits, bit k of
  *          word w = entry 32w+k of the tile, forced first bit included
+ *          (debug plans only, else zeros)
  *   int32 speculator[n_tiles * 4]      {start, stop, tile, 0} of every dirty
  *          tile, in tile order; the first dirty_count entries are valid
  *   int32 sync_idx[n_bunches]
