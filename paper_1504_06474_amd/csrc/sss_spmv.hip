@@ -5,17 +5,19 @@
 // (Section 3.1).  Per bunch:
 //   * the bunch's first row r0 = rightmost row with row_ptr[r] <= b0, by a
 //     wave-parallel 64-ary search (each round narrows the range 64x with one
-//     load per lane and a ballot);
+//     load per lane and a ballot), or read from the plan when the plan ran
+//     that search once for all calls (bound rows);
 //   * one pass over the bunch's rows in 64-row chunks builds the segment
 //     descriptor of all S tiles as a bit mask in LDS (head at row_ptr[r] - b0
 //     for each non-empty row), finds every tile's start row (the rightmost
 //     match of each tile boundary, counted by ballots) and detects the dirty
 //     tiles (an empty row among rows start..stop-1 of the tile);
 //   * per tile: coalesced vector loads of col/val (lane j owns entries
-//     [jW, jW+W)), gathers of x, products in registers, a per-lane sequential
-//     segmented reduction, a 64-lane segmented scan of the lanes' open
-//     segments (shuffles), an exclusive scan of head counts giving each partial
-//     sum its compact rank q, and the store of partial q to y[start + q].
+//     [jW, jW+W)), gathers of x, an exclusive scan of head counts giving each
+//     partial sum its compact rank q, one pass over the lane's products that
+//     stores every segment closed inside the lane, a 64-lane segmented scan
+//     of the lanes' open segments (DPP) that completes the segments crossing
+//     lanes, and the store of partial q to y[start + q].
 //     The bunch's first segment goes to the synchronizer instead; a tile that
 //     ends inside row `stop` hands its last partial to the next tile through
 //     the transmitter.  Dirty tiles are recorded, as <start, stop, tile>, in
@@ -687,8 +689,10 @@ __global__ __launch_bounds__(256) void sss_floor(MatCtx a, typename VT<DT>::y_t 
 
 // Many matrices in one persistent launch: the thread-bunches of all matrices
 // form one nnz-balanced index space (bunch_base = prefix of the per-matrix
-// bunch counts); each wavefront strides over it and finds its matrix by the
-// same rightmost-match search the method uses for rows.
+// bunch counts).  Stage 1 reads each bunch's matrix, first row and index
+// within the matrix from the plan (found at plan time by the same
+// rightmost-match search the method uses for rows); stage 2 runs that search
+// over bunch_base itself.
 struct BatchArgs {
   const MatCtx *mats;
   const int64_t *bunch_base;  // [count+1]
