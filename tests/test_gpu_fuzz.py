@@ -1,0 +1,88 @@
+"""Seeded random matrices against the oracle, bit-exact (integer values and x
+in {-3..3}): row-length mixes that stress the method's corner cases -- runs of
+empty rows, rows spanning many thread-bunches, rows ending exactly on tile
+boundaries -- under random (W, S, B), searched or bound first rows, and
+random batches with per-matrix S."""
+import numpy as np
+import pytest
+
+import csrgen
+import oracle
+from helpers import note, to_dev, assert_exact
+
+pytestmark = pytest.mark.gpu
+
+
+def random_lengths(rng, W):
+    """A row-length sequence mixing the structures the method treats
+    specially; W*64 (one tile) is used to place rows on tile boundaries."""
+    WT = W * 64
+    parts = []
+    for _ in range(int(rng.integers(1, 12))):
+        kind = int(rng.integers(0, 6))
+        k = int(rng.integers(1, 400))
+        if kind == 0:
+            parts.append(np.zeros(k, np.int64))                       # a run of empty rows
+        elif kind == 1:
+            parts.append(rng.integers(0, 12, k))                      # short rows, some empty
+        elif kind == 2:
+            parts.append(np.full(int(rng.integers(1, 4)), int(rng.integers(WT, 40 * WT))))  # rows over many tiles
+        elif kind == 3:
+            parts.append(np.full(int(rng.integers(1, 20)), WT))       # rows that are exactly one tile
+        elif kind == 4:
+            parts.append(np.full(k, int(rng.integers(1, 3))))         # many tiny rows
+        else:
+            L = rng.integers(0, 30, k)
+            L[rng.random(k) < 0.5] = 0                                 # half empty
+            parts.append(L)
+    return np.concatenate(parts)
+
+
+def random_matrix(seed, W):
+    rng = np.random.default_rng(seed)
+    lengths = random_lengths(rng, W)
+    n = int(rng.integers(1, 3000)) if rng.random() < 0.5 else int(rng.integers(50_000, 200_000))
+    lengths = np.minimum(lengths, n)  # unique columns per row
+    A = csrgen.lengths_to_csr(rng, lengths, n, "int")
+    x = csrgen.integer_values(rng, n)
+    return A, x
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_fuzz_single(seed):
+    import torch
+    from paper_1504_06474_amd import sss
+    rng = np.random.default_rng(1000 + seed)
+    W = int(rng.choice([4, 8, 16]))
+    S = int(rng.integers(1, 17))
+    B = int(rng.integers(1, 5))
+    bind = bool(rng.integers(0, 2))
+    A, x = random_matrix(seed, W)
+    note(f"  seed={seed} m={A.m} n={A.n} nnz={A.nnz} W={W} S={S} B={B} bind={bind}")
+    rp, col, v, xx = to_dev(A, x)
+    plan = sss.Plan(A.m, A.n, A.nnz, W=W, S=S, B=B, bind_rows=bind, row_ptr=rp if bind else None)
+    y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.execute(rp, col, v, xx, y)
+    torch.cuda.synchronize()
+    assert_exact(y.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fuzz_batched(seed):
+    import torch
+    from paper_1504_06474_amd import sss
+    rng = np.random.default_rng(5000 + seed)
+    W = int(rng.choice([4, 8, 16]))
+    mats = [random_matrix(10_000 * (seed + 1) + i, W) for i in range(int(rng.integers(1, 24)))]
+    descs, refs = [], []
+    for A, x in mats:
+        rp, col, v, xx = to_dev(A, x)
+        y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+        descs.append({"row_ptr": rp, "col": col, "val": v, "x": xx, "y": y, "n": A.n, "S": int(rng.integers(1, 17))})
+        refs.append(oracle.spmv(A.row_ptr, A.col, A.val, x))
+    note(f"  seed={seed} matrices={len(mats)} W={W} nnz={sum(A.nnz for A, _ in mats)}")
+    plan = sss.BatchPlan(descs, W=W)
+    plan.execute()
+    torch.cuda.synchronize()
+    for d, ref in zip(descs, refs):
+        assert_exact(d["y"].cpu().numpy(), ref)
