@@ -280,8 +280,9 @@ def host_stage2_block(torch, sss, plan, copies, A, x, reps: int = 20) -> dict:
 
 def cg_block(torch, sss, iters: int = 300) -> dict:
     """Iterative-solver use: CG on the 5-point Laplacian of a 1024 x 1024
-    grid, one bound plan reused for every product; the plan's one-off
-    analysis time, the time per iteration and the product's share of it."""
+    grid, one bound plan with the selector's (W, S) reused for every
+    product; the plan's one-off analysis time (features, the network, the
+    first-row search), the time per iteration and the product's share."""
     import csrgen
     from paper_1504_06474_amd.cg import cg
     A = csrgen.laplacian2d_csr(1024)
@@ -289,8 +290,9 @@ def cg_block(torch, sss, iters: int = 300) -> dict:
     x_true = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, A.n)).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = sss.Plan(A.m, A.n, A.nnz, W=8, S=1, bind_rows=True, row_ptr=rp)
+    plan = sss.Plan(A.m, A.n, A.nnz, mode=sss.MODE_SELECTOR, bind_rows=True, row_ptr=rp)  # learned (W, S)
     t_plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
     b = torch.empty_like(x_true)
     plan.execute(rp, col, v, x_true, b)
     cg(plan, rp, col, v, b, max_iter=10)  # warm
@@ -307,7 +309,8 @@ def cg_block(torch, sss, iters: int = 300) -> dict:
     fo = torch.empty(plan.info()["n_bunches"] * 64, dtype=torch.float64, device="cuda")
     fl_us = graph_time_us(torch, lambda c: plan.floor_probe(c[1], c[2], c[3], fo, True), [(rp, col, v, x_true, y)])
     byts = alg_bytes(A.m, A.n, A.nnz, 8, 8)
-    out = {"workload": "laplacian2d_1024", "m": A.m, "nnz": A.nnz, "W": 8, "S": 1, "plan_ms": round(t_plan_ms, 3),
+    out = {"workload": "laplacian2d_1024", "m": A.m, "nnz": A.nnz, "W": info["W"], "S": info["S"],
+           "plan_ms": round(t_plan_ms, 3),
            "iterations": it, "us_per_iteration": round(it_us, 2), "spmv_us": round(spmv_us, 2),
            "spmv_alg_GBps": round(byts / (spmv_us * 1e-6) / 1e9, 1), "stage1_us": round(s1_us, 2),
            "stream_gather_floor_us": round(fl_us, 2),
