@@ -191,12 +191,13 @@ def test_misaligned_pointers_rejected(torch_cuda):
         plan.execute(rp, colx[1:], v, xx)
 
 
-@pytest.mark.parametrize("WS", [(8, 5), (4, 8), (16, 2)])
-def test_config2_full_size_f64(torch_cuda, WS):
-    """The 1M-row power-law matrix: every row against the oracle."""
+@pytest.mark.parametrize("WS,bind", [((8, 5), True), ((8, 5), False), ((4, 8), False), ((16, 2), True)])
+def test_config2_full_size_f64(torch_cuda, WS, bind):
+    """The 1M-row power-law matrix: every row against the oracle; W=8, S=5
+    with bound rows is the benchmark's launch configuration."""
     A, x = _config2_cached()
-    note(f"  powerlaw1e6 nnz={A.nnz} W,S={WS}")
-    y, _ = run_plan(torch_cuda, A, x, W=WS[0], S=WS[1])
+    note(f"  powerlaw1e6 nnz={A.nnz} W,S={WS} bind={bind}")
+    y, _ = run_plan(torch_cuda, A, x, W=WS[0], S=WS[1], bind_rows=bind)
     ref, scale = _config2_ref()
     assert_f64_parity(y, ref, scale)
 

@@ -16,7 +16,7 @@ from helpers import note, to_dev_precision, assert_exact, assert_f32_path_bound,
 
 pytestmark = pytest.mark.gpu
 
-DT = {"f32": "float32", "bf16": "bfloat16"}
+DT = {"f64": "float64", "f32": "float32", "bf16": "bfloat16"}
 
 
 @pytest.fixture(scope="module")
@@ -34,10 +34,11 @@ def _announce(request):
     yield
 
 
-def run(torch, A, x, kind, W=0, S=0):
+def run(torch, A, x, kind, W=0, S=0, bind=False):
     from paper_1504_06474_amd import sss
     rp, col, v, xx, ve, xe = to_dev_precision(A, x, kind)
-    plan = sss.Plan(A.m, A.n, A.nnz, dtype=getattr(torch, DT[kind]), W=W, S=S)
+    plan = sss.Plan(A.m, A.n, A.nnz, dtype=getattr(torch, DT[kind]), W=W, S=S, bind_rows=bind,
+                    row_ptr=rp if bind else None)
     y = plan.execute(rp, col, v, xx)
     torch.cuda.synchronize()
     return y.double().cpu().numpy(), ve, xe
@@ -80,3 +81,25 @@ def test_config2_full_size(torch_cuda, kind):
     y, ve, xe = run(torch_cuda, A, x, kind)
     ref = oracle.spmv(A.row_ptr, A.col, ve, xe)
     assert_f32_path_bound(y, ref, oracle.abs_spmv(A.row_ptr, A.col, ve, xe))
+
+
+_C5 = {}
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32", "bf16"])
+def test_config5_full_size(torch_cuda, kind):
+    """The 4M-row Zipf 1.8 matrix (80.3M nnz) in the benchmark's launch
+    configuration (the type's default W and S, rows bound at plan time):
+    every row against the oracle on the stored values."""
+    from helpers import assert_f64_parity
+    if not _C5:
+        _C5["A"], _C5["x"] = csrgen.config5()
+    A, x = _C5["A"], _C5["x"]
+    note(f"  zipf18_4M nnz={A.nnz} {kind}")
+    y, ve, xe = run(torch_cuda, A, x, kind, bind=True)
+    ref = oracle.spmv(A.row_ptr, A.col, ve, xe)
+    scale = oracle.abs_spmv(A.row_ptr, A.col, ve, xe)
+    if kind == "f64":
+        assert_f64_parity(y, ref, scale)
+    else:
+        assert_f32_path_bound(y, ref, scale)
