@@ -258,7 +258,7 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
 
 /* Row-wise comparator, NOT the speculative method: the row-based GPU
  * kernels the paper measures against (Section 4.3, CSR-scalar and
- * CSR-vector; Section 2.2 explains their load imbalance on irregular
+ * CSR-vector; Section 2.1 explains their load imbalance on irregular
  * matrices), written for gfx950.  lanes_per_row = 1 is CSR-scalar (a thread
  * per row), 64 is CSR-vector (a wavefront per row), powers of two between
  * give sub-wavefront groups; a row's lanes stride over it and reduce by

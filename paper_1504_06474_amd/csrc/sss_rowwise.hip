@@ -2,7 +2,7 @@
 //
 // The paper measures the speculative segmented sum against row-wise GPU
 // kernels (Section 4.3): "CSR-scalar", one thread per row, and "CSR-vector",
-// one SIMD unit per row with a reduction across its lanes.  Section 2.2
+// one SIMD unit per row with a reduction across its lanes.  Section 2.1
 // explains why they lose on irregular matrices: a thread or wavefront that
 // owns a long row serialises it while its neighbours idle, and short rows
 // leave lanes idle in the vector form.  These kernels are written here from
