@@ -1,4 +1,4 @@
-/* Test driver (CPU only): runs every entry point of the C oracle on small
+/* Test program (CPU only): runs every entry point of the C oracle on small
  * matrices -- m = 0, nnz = 0, ragged rows with empty ones, a dense row --
  * with 1 and 3 threads, under AddressSanitizer and UndefinedBehaviorSanitizer
  * (built by tests/test_oracle_sanitize.py).  Integer-valued inputs, so the

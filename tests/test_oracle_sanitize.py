@@ -1,5 +1,5 @@
 """The C oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
-(gcc, CPU only) and run through every entry point by a small driver: no
+(gcc, CPU only) and run through every entry point by a small test program: no
 out-of-bounds access, no undefined behaviour, the four functions agree on
 integer-valued inputs."""
 import os
