@@ -61,21 +61,51 @@ def measured_traffic(W: int, S: int, B: int, bind_rows: bool):
     return int(rec["fetch_kib_raw"] * rec["fetch_factor"] * 1024 + rec["write_kib_raw"] * rec["write_factor"] * 1024)
 
 
-def cpu_baseline(A, x, seconds: float) -> dict:
-    import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    oracle.spmv(A.row_ptr, A.col, A.val, x, threads)  # warm caches / page in
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_reps(fn, seconds: float):
+    """Repetitions of fn() and the seconds they took, at least one, about `seconds`."""
     reps, t0 = 0, time.perf_counter()
     while True:
-        oracle.spmv(A.row_ptr, A.col, A.val, x, threads)
+        fn()
         reps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
-            break
+            return reps, el
+
+
+def cpu_baseline(A, x, seconds: float) -> dict:
+    """The oracle on the host cores (the graded baseline), then the paper's
+    CPU comparators on the same matrix (Section 4.3): the oracle's Dot2 row
+    loop on one thread, the plain OpenMP row-block loop, and the plain
+    single-thread loop.  Each comparator gets a fifth of `seconds`."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    oracle.spmv(A.row_ptr, A.col, A.val, x, threads)  # warm caches / page in
+    reps, el = _time_reps(lambda: oracle.spmv(A.row_ptr, A.col, A.val, x, threads), seconds)
     gflops = 2.0 * A.nnz * reps / el / 1e9
+    nbytes = A.nnz * 12 + (A.m + 1) * 4 + A.n * 8 + A.m * 8
+    comparators = {}
+    for name, t, fn in (
+            ("dot2_1_thread", 1, lambda: oracle.spmv(A.row_ptr, A.col, A.val, x, 1)),
+            ("rowblock_openmp", threads, lambda: oracle.spmv_rowblock(A.row_ptr, A.col, A.val, x, threads)),
+            ("naive_1_thread", 1, lambda: oracle.spmv_naive(A.row_ptr, A.col, A.val, x))):
+        r, e = _time_reps(fn, seconds / 5)
+        comparators[name] = {"GFLOPs": round(2.0 * A.nnz * r / e / 1e9, 3), "GBps": round(nbytes * r / e / 1e9, 2),
+                             "threads": t, "reps": r}
     return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"the full benchmark matrix ({A.nnz} nnz), {reps} repetitions of the Dot2 FP64 "
-                      f"row loop with OpenMP over rows, {el:.1f} s"}
+                      f"row loop with OpenMP over rows, {el:.1f} s",
+            "cpu_model": _cpu_model(), "comparators": comparators}
 
 
 def time_steps(torch, plan, copies, steps: int, warmup: int) -> float:
