@@ -83,6 +83,39 @@ def _time_reps(fn, seconds: float):
             return reps, el
 
 
+def _finite(v):
+    """The JSON line holds no NaN or infinity: such a figure (a block that was
+    skipped, an empty sample) becomes null."""
+    if isinstance(v, dict):
+        return {k: _finite(u) for k, u in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(u) for u in v]
+    if isinstance(v, float) and not np.isfinite(v):
+        return None
+    return v
+
+
+def row_sums(row_ptr, col, val, x):
+    """Reference for the error figures this script reports: y_i = sum of
+    val*x[col] over row i, and (|A||x|)_i, both summed in long double (64-bit
+    mantissa) and rounded to double.  Each product carries a relative error
+    below 2^-64 and the sums of up to 2*10^5 terms stay within ~1e-14 of
+    (|A||x|)_i of the exact values: far inside the 1e-12 checks.  Plain
+    numpy, independent of the library."""
+    if np.finfo(np.longdouble).nmant < 63:
+        raise RuntimeError("long double is not the 64-bit-mantissa extended type on this host")
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    m = rp.shape[0] - 1
+    p = np.asarray(val, dtype=np.longdouble) * np.asarray(x, dtype=np.longdouble)[np.asarray(col)]
+    y = np.zeros(m, dtype=np.longdouble)
+    sc = np.zeros(m, dtype=np.longdouble)
+    rows = np.flatnonzero(rp[1:] > rp[:-1])  # a non-empty row's entries run to the next non-empty row's start
+    if rows.size:
+        y[rows] = np.add.reduceat(p, rp[rows])
+        sc[rows] = np.add.reduceat(np.abs(p), rp[rows])
+    return y.astype(np.float64), sc.astype(np.float64)
+
+
 def cpu_baseline(A, x, seconds: float) -> dict:
     """The oracle on the host cores (the graded baseline), then the paper's
     CPU comparators on the same matrix (Section 4.3): the oracle's Dot2 row
@@ -189,9 +222,9 @@ def rowwise_comparison(torch, sss, copies, n: int, sss_call) -> dict:
 
 def precision_block(torch, sss, steps: int, warmup: int) -> dict:
     """The 4M-row Zipf-1.8 matrix stored FP64 / FP32 / BF16: time per y = A x
-    and the error against the FP64 oracle, for uniform and lognormal values."""
+    and the error against the exact product of the FP64 values (row_sums), for
+    uniform and lognormal values."""
     import csrgen
-    import oracle
     log("[bench] precision: generating the 4M-row Zipf 1.8 matrix (seed 5)")
     A, x = csrgen.config5()
     out = {"workload": "zipf18_4M", "m": A.m, "nnz": A.nnz}
@@ -199,8 +232,7 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
     tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
     for values in ("uniform", "lognormal"):
         Av = A if values == "uniform" else csrgen.with_values(A, "lognormal", 55)
-        ref64 = oracle.spmv(Av.row_ptr, Av.col, Av.val, x)
-        sc64 = oracle.abs_spmv(Av.row_ptr, Av.col, Av.val, x)
+        ref64, sc64 = row_sums(Av.row_ptr, Av.col, Av.val, x)
         for kind in ("f64", "f32", "bf16"):
             vs, xs, ve, xe = csrgen.quantize(Av, x, kind)
             rp = torch.from_numpy(Av.row_ptr).cuda()
@@ -260,10 +292,9 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                 plan.execute(rp, col, v, xx, y)
             torch.cuda.synchronize()
             yh = y.double().cpu().numpy()
-            rec.setdefault("err_vs_f64_oracle", {})[values] = error_stats(yh, ref64, sc64)
+            rec.setdefault("err_vs_f64", {})[values] = error_stats(yh, ref64, sc64)
             if kind != "f64":
-                refq = oracle.spmv(Av.row_ptr, Av.col, ve, xe)
-                scq = oracle.abs_spmv(Av.row_ptr, Av.col, ve, xe)
+                refq, scq = row_sums(Av.row_ptr, Av.col, ve, xe)
                 rec.setdefault("err_arith_only", {})[values] = error_stats(yh, refq, scq)
             del rp, col, v, xx, y
             plan.close()
@@ -280,7 +311,6 @@ def host_stage2_block(torch, sss, plan, copies, A, x, reps: int = 20) -> dict:
     """The paper's split on this discrete GPU: stage 1 on the device, y and
     the plan's small arrays to host memory, stage 2 on one host core, y back;
     against the device stage 2 (the product path).  Wall-clock per call."""
-    import oracle
     y_pin = torch.empty(A.m, dtype=torch.float64, pin_memory=True)
     parts = np.zeros((reps, 3))
     for k in range(reps + 2):
@@ -299,9 +329,9 @@ def host_stage2_block(torch, sss, plan, copies, A, x, reps: int = 20) -> dict:
         if k >= 2:
             parts[k - 2] = (t1 - t0, t2 - t1, t3 - t2)
     rows = np.random.default_rng(1).choice(A.m, size=500, replace=False)
-    ref = oracle.spmv_rows(A.row_ptr, A.col, A.val, x, rows)
+    ref, scale = row_sums(A.row_ptr, A.col, A.val, x)
+    ref, scale = ref[rows], scale[rows]
     got = copies[(reps + 1) % len(copies)][4].cpu().numpy()[rows]
-    scale = oracle.abs_spmv(A.row_ptr, A.col, A.val, x)[rows]
     mean = [float(v) for v in parts.mean(axis=0) * 1e6]
     return {"stage1_and_copy_to_host_us": round(mean[0], 1), "host_stage2_us": round(mean[1], 1),
             "copy_back_us": round(mean[2], 1), "total_us": round(sum(mean), 1),
@@ -356,13 +386,11 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
     per stage, eager and as a replayed HIP graph) against 512 separate plans
     launched one after another (eager and captured in a graph)."""
     import csrgen
-    import oracle
     log("[bench] batched: generating 512 matrices (seeds 20000..20511)")
     mats = csrgen.batched_set(512)
     out = {"workload": "batch512_zipf2", "count": len(mats), "sum_m": int(sum(A.m for A, _ in mats)),
            "sum_nnz": int(sum(A.nnz for A, _ in mats))}
-    refs = [oracle.spmv(A.row_ptr, A.col, A.val, x) for A, x in mats]
-    scales = [oracle.abs_spmv(A.row_ptr, A.col, A.val, x) for A, x in mats]
+    refs, scales = zip(*[row_sums(A.row_ptr, A.col, A.val, x) for A, x in mats])
 
     def timed(fn, k):
         for _ in range(warmup):
@@ -430,13 +458,13 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
                      "speedup_vs_separate_graph": round(ms_sep_graph / ms_batch, 2),
                      "batched_GFLOPs": round(2 * out["sum_nnz"] / (ms_batch * 1e-3) / 1e9, 1),
                      "batched_alg_GBps": round(byts / (ms_batch * 1e-3) / 1e9, 1),
-                     "max_err_scaled_vs_f64_oracle": worst,
+                     "max_err_scaled_vs_f64": worst,
                      "autotuned": {"W": ginfo["W"], "S": ginfo["S"], "grid_class_us": [round(float(t), 1) for t in grid_us],
                                    "batched_us": round(ms_grid * 1e3, 1),
                                    "batched_graph_us": round(ms_grid_graph * 1e3, 1),
                                    "speedup_vs_separate": round(ms_sep / ms_grid, 2),
                                    "speedup_vs_separate_graph": round(ms_sep_graph / ms_grid, 2),
-                                   "max_err_scaled_vs_f64_oracle": worst_grid}}
+                                   "max_err_scaled_vs_f64": worst_grid}}
         log(f"[bench] batched {kind}: {out[kind]}")
         del g, plans, bp, dev
         torch.cuda.synchronize()
@@ -682,16 +710,17 @@ def main():
     torch.cuda.synchronize()
     ms_warm = ev0.elapsed_time(ev1) / args.steps
 
-    # correctness of the benchmarked launch configuration, sampled rows
-    import oracle
-    rows = np.random.default_rng(0).choice(m, size=2000, replace=False)
-    rows = np.concatenate([rows, [int(np.argmax(np.diff(A.row_ptr)))]])
+    # correctness of the benchmarked launch configuration: every row, within
+    # 1e-12 of (|A||x|)_i; the plain relative error over rows that do not
+    # cancel (|y_i| >= 1e-3 (|A||x|)_i)
     y0 = copies[0][4].cpu().numpy()
-    ref = oracle.spmv_rows(A.row_ptr, A.col, A.val, x, rows)
-    scale = np.abs(np.asarray([sum(abs(A.val[k] * x[A.col[k]]) for k in range(A.row_ptr[r], A.row_ptr[r + 1]))
-                               for r in rows[:200]]))
-    err_ok = bool(np.all(np.abs(y0[rows[:200]] - ref[:200]) <= 1e-12 * scale))
-    max_rel = float(np.max(np.abs(y0[rows] - ref) / np.maximum(np.abs(ref), 1e-300)))
+    ref, scale = row_sums(A.row_ptr, A.col, A.val, x)
+    err = np.abs(y0 - ref)
+    err_ok = bool(np.all(err <= 1e-12 * scale))
+    max_scaled = float(np.max(err / np.where(scale > 0, scale, 1.0)))
+    big = (scale > 0) & (np.abs(ref) >= 1e-3 * scale)
+    max_rel = float(np.max(err[big] / np.abs(ref[big]))) if big.any() else 0.0
+    del ref, scale, err, big
 
     B = alg_bytes(m, n, nnz, 8, 8)
     achieved = B / (s1_ms * 1e-3) / 1e9
@@ -731,8 +760,9 @@ def main():
                        "stage1_frac_of_stream_gather_floor": round(floors["stream_gather_us"] / (s1_ms * 1e3), 3)},
             "vs_rowwise": comp_c2,
             "stage2_on_host": host_s2,
-            "sampled_rows_within_1e-12": err_ok,
-            "sampled_max_rel_err": max_rel,
+            "all_rows_within_1e-12": err_ok,
+            "max_err_over_abs_Ax": max_scaled,
+            "max_rel_err": max_rel,
         },
     }
     if not args.skip_selector:
@@ -747,7 +777,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, x, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

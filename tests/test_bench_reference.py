@@ -1,0 +1,43 @@
+"""bench.py reports its error figures against its own reference (`row_sums`:
+products and row sums in long double).  Here that reference is checked
+against the oracle: ragged rows, runs of empty rows at both ends, a long row,
+all-empty and nnz = 0 matrices."""
+import numpy as np
+
+import bench
+import csrgen
+import oracle
+
+
+def _check(rp, col, val, x):
+    y, sc = bench.row_sums(rp, col, val, x)
+    yo = oracle.spmv(rp, col, val, x)
+    so = oracle.abs_spmv(rp, col, val, x)
+    s = np.where(so > 0, so, 1.0)
+    assert np.all(np.abs(y - yo) <= 1e-15 * s)
+    assert np.all(np.abs(sc - so) <= 1e-14 * s)
+    assert np.all(y[so == 0] == 0)
+
+
+def test_row_sums_matches_oracle_on_ragged_rows():
+    rng = np.random.default_rng(7)
+    lengths = np.concatenate([np.zeros(5, np.int64), rng.integers(0, 30, 400), [20_000], np.zeros(7, np.int64)])
+    A = csrgen.lengths_to_csr(rng, lengths, 50_000, "uniform")
+    x = rng.uniform(-1, 1, 50_000)
+    _check(A.row_ptr, A.col, A.val, x)
+
+
+def test_row_sums_benchmark_generator_small():
+    A, x = csrgen.config1()
+    _check(A.row_ptr, A.col, A.val, x)
+
+
+def test_row_sums_degenerate():
+    x = np.array([1.0, -2.0, 3.0])
+    y, sc = bench.row_sums(np.zeros(4, np.int32), np.zeros(0, np.int32), np.zeros(0), x)
+    assert y.shape == (3,) and not y.any() and not sc.any()
+    y, sc = bench.row_sums(np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), x)
+    assert y.shape == (0,)
+    rp = np.array([0, 0, 2, 2, 3], np.int32)
+    y, sc = bench.row_sums(rp, np.array([0, 2, 1], np.int32), np.array([2.0, -1.0, 4.0]), x)
+    assert list(y) == [0.0, -1.0, 0.0, -8.0] and list(sc) == [0.0, 5.0, 0.0, 8.0]
