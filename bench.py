@@ -532,9 +532,8 @@ def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
     return out
 
 
-def run_copy_calibration(steps: int):
-    import torch
-    nbytes = 1 << 30
+def device_copy_ms(torch, steps: int, nbytes: int = 1 << 30) -> float:
+    """Average ms of a plain device-to-device copy of nbytes (torch's copy_)."""
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -546,7 +545,13 @@ def run_copy_calibration(steps: int):
         dst.copy_(src)
     ev1.record()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / steps
+    return ev0.elapsed_time(ev1) / steps
+
+
+def run_copy_calibration(steps: int):
+    import torch
+    nbytes = 1 << 30
+    ms = device_copy_ms(torch, steps, nbytes)
     print(json.dumps({"mode": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
                       "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
@@ -650,6 +655,18 @@ def main():
     s2_ms = float(s2.mean())
     log(f"[bench] stage1 {s1_ms * 1e3:.2f} us, stage2 {s2_ms * 1e3:.2f} us")
 
+    # the distribution of whole steps: events around every step (the headline
+    # above is the bracketed K-step time)
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        ea[k].record()
+        step(k)
+        eb[k].record()
+    torch.cuda.synchronize()
+    st = np.array([ea[k].elapsed_time(eb[k]) for k in range(args.steps)]) * 1e3
+    per_step = {"mean": round(float(st.mean()), 2), "median": round(float(np.median(st)), 2),
+                "p10": round(float(np.percentile(st, 10)), 2), "p90": round(float(np.percentile(st, 90)), 2)}
+
     # memory floors of stage 1's access pattern with the same tiling and the
     # same rotated copies: col/val streamed alone, and streamed with x gathered
     floor_out = torch.empty(info["n_bunches"] * 64, dtype=torch.float64, device="cuda")
@@ -668,6 +685,12 @@ def main():
         floors[name] = float(np.mean([ea[k].elapsed_time(eb[k]) for k in range(args.steps)])) * 1e3
     del floor_out
     log(f"[bench] floors {floors}")
+
+    # a plain device copy on the same device: the practical streaming rate
+    copy_GBps = None
+    if not args.skip_extras:
+        copy_GBps = round(2 * (1 << 30) / (device_copy_ms(torch, 10) * 1e-3) / 1e9, 1)
+        log(f"[bench] device copy {copy_GBps} GB/s (read + write)")
 
     # the other plan variant (first rows searched in every call, or bound)
     ms_other = s1_other = float("nan")
@@ -751,6 +774,8 @@ def main():
             "stage2_us": round(s2_ms * 1e3, 2),
             ("searching_plan" if bind else "bound_rows_plan"): None if args.skip_extras else {
                 "us_per_step": round(ms_other * 1e3, 2), "stage1_us": round(s1_other * 1e3, 2)},
+            "per_step_us": per_step,
+            "device_copy_GBps": copy_GBps,
             "warm_cache_us_per_step": round(ms_warm * 1e3, 2),
             "warm_cache_GFLOPs": round(2.0 * nnz / (ms_warm * 1e-3) / 1e9, 2),
             "paper_formula_GBps": round(paper_bytes(m, nnz, 8) / (ms_step * 1e-3) / 1e9, 1),
