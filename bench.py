@@ -414,6 +414,11 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
         info = bp.info()
         ms_batch = timed(bp.execute, steps)
         ms_graph = timed(bp.graph_launch, steps)
+        # the same plan with a persistent stage 1 (batch_persistent)
+        bp_p = sss.BatchPlan(dev, dtype=tdt, persistent=True)
+        ms_persistent = timed(bp_p.execute, steps)
+        bp_p.close()
+        bp.execute()  # the checked output below is the default plan's
         # correctness of the batched result (every matrix, every row)
         worst = 0.0
         for (A, x), d, ref, sc in zip(mats, dev, refs, scales):
@@ -453,6 +458,7 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
         byts = sum(alg_bytes(A.m, A.n, A.nnz, vb, vb) for A, _ in mats)
         out[kind] = {"W": info["W"], "S": info["S"], "n_bunches": info["n_bunches"],
                      "batched_us": round(ms_batch * 1e3, 1), "batched_graph_us": round(ms_graph * 1e3, 1),
+                     "persistent_stage1_us": round(ms_persistent * 1e3, 1),
                      "separate_us": round(ms_sep * 1e3, 1), "separate_graph_us": round(ms_sep_graph * 1e3, 1),
                      "speedup_vs_separate": round(ms_sep / ms_batch, 2),
                      "speedup_vs_separate_graph": round(ms_sep_graph / ms_batch, 2),

@@ -94,6 +94,11 @@ typedef struct {
                     row_ptr (required); execute then reads those rows instead
                     of searching, and the plan serves only matrices whose
                     row_ptr has the same contents */
+  int batch_persistent; /* batch plans only.  0 (default): stage 1 launches one
+                           wavefront per thread-bunch of every matrix.  Nonzero:
+                           stage 1 is a persistent grid (as many workgroups as
+                           stay resident) whose wavefronts loop over the
+                           bunches.  Same results; the default measured faster. */
 } sss_plan_opts;
 
 typedef struct sss_plan_s *sss_plan;
@@ -168,11 +173,14 @@ typedef struct {
   int reserved;
 } sss_csr_desc;
 
-/* A batch plan: y_i = A_i x_i for `count` matrices in one persistent launch
- * per stage.  The thread-bunches of all matrices form one nnz-balanced index
- * space (Section 3.1's decomposition applied to the concatenation); each
- * wavefront finds its matrix with the same rightmost-match search the method
- * uses for rows (Section 3.2).  All matrices share dtype and W (opts); each
+/* A batch plan: y_i = A_i x_i for `count` matrices in one launch per stage.
+ * The thread-bunches of all matrices form one nnz-balanced index space
+ * (Section 3.1's decomposition applied to the concatenation); the plan finds
+ * each bunch's matrix with the same rightmost-match search the method uses
+ * for rows (Section 3.2).  Stage 1 runs one wavefront per bunch, each XCD
+ * taking a contiguous run of the bunch space (opts->batch_persistent: a
+ * persistent grid instead); stage 2 is a persistent grid.  All matrices
+ * share dtype and W (opts); each
  * may set its own S.  The descriptors' pointers are bound to the plan: the
  * plan must be recreated if a matrix or vector moves.  Different matrices
  * must not share y storage.  Allocates (the descriptors, prefix arrays and

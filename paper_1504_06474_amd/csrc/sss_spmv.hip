@@ -687,7 +687,7 @@ __global__ __launch_bounds__(256) void sss_floor(MatCtx a, typename VT<DT>::y_t 
   out[tb * kWave + lane] = (typename VT<DT>::y_t)acc;
 }
 
-// Many matrices in one persistent launch: the thread-bunches of all matrices
+// Many matrices in one launch per stage: the thread-bunches of all matrices
 // form one nnz-balanced index space (bunch_base = prefix of the per-matrix
 // bunch counts).  Stage 1 reads each bunch's matrix, first row and index
 // within the matrix from the plan (found at plan time by the same
@@ -715,12 +715,35 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   uint32_t *lds_wave = lds_words + wid * stage1_lds_words(W, b.S_max);
-  // XCD-aware split: the workgroups with b mod G = k stride over the k-th
-  // contiguous G-th of the global bunch space.  Each XCD then works through
-  // its own run of matrices, and its L2 holds the x of the few matrices in
-  // its window instead of those of every matrix in flight on the chip.  (The
-  // split is correct for any placement of workgroups; the placement only
-  // decides the speed.)
+  // One wavefront per thread-bunch, XCD-aware: the grid is a multiple of G
+  // workgroups (or fewer than G), and workgroup blockIdx.x, which runs on XCD
+  // blockIdx.x mod G, takes the (blockIdx.x / G)-th workgroup's worth of
+  // bunches of that XCD's contiguous G-th of the global bunch space.  Each
+  // XCD then works through its own run of matrices in order, and its L2
+  // holds the x of the few matrices in its window instead of those of every
+  // matrix in flight on the chip.  (Any placement of workgroups gives the
+  // same result; the placement only decides the speed.)
+  const int G = min((int)gridDim.x, kXcds);
+  const int64_t per = gridDim.x / G;
+  const int64_t wg = (int64_t)(blockIdx.x % G) * per + blockIdx.x / G;
+  const int64_t g = wg * (blockDim.x / kWave) + wid;
+  if (g >= b.total_bunches) return;
+  const int4 bi = b.bunch_info[g];
+  const MatCtx a = b.mats[bi.x];
+  stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.y);
+}
+
+
+// The same work as a persistent grid (batch_persistent plans): as many
+// workgroups as stay resident, a multiple of G; the workgroups with
+// blockIdx.x mod G = k stride over the k-th contiguous G-th of the global
+// bunch space, one bunch per wavefront per step.
+template <int DT, int W>
+__global__ __launch_bounds__(256) void sss_stage1_batch_persistent(BatchArgs b) {
+  extern __shared__ uint32_t lds_words[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  uint32_t *lds_wave = lds_words + wid * stage1_lds_words(W, b.S_max);
   const int G = min((int)gridDim.x, kXcds);
   const int k = (int)(blockIdx.x % G);
   const int wpb = blockDim.x / kWave;
@@ -732,7 +755,6 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
     stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.y);
   }
 }
-
 
 // ---------------------------------------------------------------- stage 2
 
@@ -981,20 +1003,20 @@ Stage1Fn pick_stage1(int dt, int W, bool dbg) {
 }
 
 template <int DT>
-BatchFn pick_batch_w(int W) {
+BatchFn pick_batch_w(int W, bool persistent) {
   switch (W) {
-    case 4: return sss_stage1_batch<DT, 4>;
-    case 8: return sss_stage1_batch<DT, 8>;
-    case 16: return sss_stage1_batch<DT, 16>;
+    case 4: return persistent ? sss_stage1_batch_persistent<DT, 4> : sss_stage1_batch<DT, 4>;
+    case 8: return persistent ? sss_stage1_batch_persistent<DT, 8> : sss_stage1_batch<DT, 8>;
+    case 16: return persistent ? sss_stage1_batch_persistent<DT, 16> : sss_stage1_batch<DT, 16>;
     default: return nullptr;
   }
 }
 
-BatchFn pick_stage1_batch(int dt, int W) {
+BatchFn pick_stage1_batch(int dt, int W, bool persistent) {
   switch (dt) {
-    case SSS_F64: return pick_batch_w<SSS_F64>(W);
-    case SSS_F32: return pick_batch_w<SSS_F32>(W);
-    case SSS_BF16: return pick_batch_w<SSS_BF16>(W);
+    case SSS_F64: return pick_batch_w<SSS_F64>(W, persistent);
+    case SSS_F32: return pick_batch_w<SSS_F32>(W, persistent);
+    case SSS_BF16: return pick_batch_w<SSS_BF16>(W, persistent);
     default: return nullptr;
   }
 }
@@ -1020,6 +1042,7 @@ struct sss_plan_s {
   uint32_t *dbg_heads = nullptr;
   // batch plans only
   bool batch = false;
+  bool batch_persistent = false;
   BatchArgs bargs{};
   int blocks1 = 0, blocks2 = 0, wpb2 = 1;
   hipStream_t capture_stream = nullptr;
@@ -1143,12 +1166,13 @@ int launch(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *v
   return launch_stage2(p, row_ptr, y, stream);
 }
 
-// Both stages of a batch plan: the persistent stage-1 launch, then the
-// persistent stage-2 launch.
+// Both stages of a batch plan: the stage-1 launch (one wavefront per
+// thread-bunch of every matrix, or the persistent form), then the persistent
+// stage-2 launch.
 int launch_batch(sss_plan p, hipStream_t stream) {
   if (p->bargs.total_waves == 0) return SSS_OK;
   if (p->bargs.total_bunches > 0) {
-    BatchFn k1 = pick_stage1_batch(p->dt, p->W);
+    BatchFn k1 = pick_stage1_batch(p->dt, p->W, p->batch_persistent);
     if (!k1) return SSS_ERR_UNSUPPORTED;
     const size_t lds1 = (size_t)p->B * stage1_lds_words(p->W, p->bargs.S_max) * sizeof(uint32_t);
     hipLaunchKernelGGL(k1, dim3((unsigned)p->blocks1), dim3(p->B * kWave), lds1, stream, p->bargs);
@@ -1438,7 +1462,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   const size_t o_bi = off; off = align256(off + sizeof(int4) * (size_t)(nb_all + 1));
 
   sss_plan p = new sss_plan_s();
-  p->batch = true; p->dt = dt; p->W = W; p->S = S; p->B = B;
+  p->batch = true; p->dt = dt; p->W = W; p->S = S; p->B = B; p->batch_persistent = o.batch_persistent != 0;
   p->m = tot_m; p->n = tot_n; p->nnz = tot_nnz; p->n_tiles = tot_tiles; p->n_bunches = nb_all;
   auto fail = [&](hipError_t e) {
     g_last_hip = e;
@@ -1486,23 +1510,39 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(e);
   }
-  // persistent grids: as many workgroups as stay resident on the device
+  // stage 2's persistent grid: as many workgroups as stay resident on the device
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) return fail(e);
-  int per_cu1 = 0, per_cu2 = 0;
-  BatchFn k1 = pick_stage1_batch(dt, W);
-  const size_t lds1 = (size_t)B * stage1_lds_words(W, s_max) * sizeof(uint32_t);
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, reinterpret_cast<const void *>(k1), B * kWave, lds1);
-  if (e != hipSuccess) return fail(e);
+  int per_cu2 = 0;
   p->wpb2 = fixup_waves_per_block(W, dt);
   const size_t lds2 = (size_t)p->wpb2 * WT * y_size(dt);
   const void *k2 = dt == SSS_F64 ? reinterpret_cast<const void *>(sss_fixup_batch<double>)
                                  : reinterpret_cast<const void *>(sss_fixup_batch<float>);
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k2, p->wpb2 * kWave, lds2);
   if (e != hipSuccess) return fail(e);
-  p->blocks1 = (int)std::max<int64_t>(1, std::min<int64_t>((nb_all + B - 1) / B, (int64_t)cus * std::max(per_cu1, 1)));
-  if (p->blocks1 > kXcds) p->blocks1 -= p->blocks1 % kXcds;  // the same number of workgroups on every XCD
+  // stage 1: B bunches per workgroup, the count rounded up to a multiple of
+  // kXcds so that every XCD gets an equal contiguous run (the extra
+  // wavefronts find no bunch and exit); persistent: as many workgroups as
+  // stay resident, a multiple of kXcds
+  int64_t wgs1 = std::max<int64_t>(1, (nb_all + B - 1) / B);
+  if (p->batch_persistent) {
+    int per_cu1 = 0;
+    const size_t lds1 = (size_t)B * stage1_lds_words(W, s_max) * sizeof(uint32_t);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu1, reinterpret_cast<const void *>(pick_stage1_batch(dt, W, true)), B * kWave, lds1);
+    if (e != hipSuccess) return fail(e);
+    wgs1 = std::min<int64_t>(wgs1, (int64_t)cus * std::max(per_cu1, 1));
+    if (wgs1 > kXcds) wgs1 -= wgs1 % kXcds;
+  } else if (wgs1 > kXcds) {
+    wgs1 = (wgs1 + kXcds - 1) / kXcds * kXcds;
+  }
+  if (wgs1 > INT32_MAX) {  // more bunches than a grid holds: beyond any batch that fits in memory
+    (void)hipFree(p->aux);
+    delete p;
+    return SSS_ERR_INVALID_VALUE;
+  }
+  p->blocks1 = (int)wgs1;
   p->blocks2 = (int)std::max<int64_t>(
       1, std::min<int64_t>((ba.total_waves + p->wpb2 - 1) / p->wpb2, (int64_t)cus * std::max(per_cu2, 1)));
   *out = p;

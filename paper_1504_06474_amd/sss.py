@@ -49,7 +49,7 @@ class CsrDesc(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int), ("B", ctypes.c_int),
-                ("debug", ctypes.c_int), ("bind_rows", ctypes.c_int)]
+                ("debug", ctypes.c_int), ("bind_rows", ctypes.c_int), ("batch_persistent", ctypes.c_int)]
 
 
 _lib = None
@@ -253,16 +253,18 @@ class Plan:
 
 
 class BatchPlan:
-    """y_i = A_i x_i for many matrices in one persistent launch per stage
+    """y_i = A_i x_i for many matrices in one launch per stage
     (sss_batch_plan_create).  `mats` is a list of (row_ptr, col, val, x, y, n)
     device tensors (n = number of columns) or dicts with those keys and an
     optional per-matrix "S".  The tensors must stay alive and in place for the
-    plan's lifetime."""
+    plan's lifetime.  persistent=True makes stage 1 a persistent grid instead
+    of one wavefront per thread-bunch."""
 
-    def __init__(self, mats, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0, stream=None):
+    def __init__(self, mats, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0, stream=None,
+                 persistent: bool = False):
         L = lib()
         descs = self._describe(mats, dtype)
-        opts = PlanOpts(MODE_FIXED, W, S, B, 0)
+        opts = PlanOpts(MODE_FIXED, W, S, B, 0, 0, 1 if persistent else 0)
         h = ctypes.c_void_p()
         _check(L.sss_batch_plan_create(len(mats), descs, self.dt, ctypes.byref(opts), _stream(stream),
                                        ctypes.byref(h)), "sss_batch_plan_create")

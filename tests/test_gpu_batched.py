@@ -1,5 +1,6 @@
-"""Batched path: many uneven matrices in one persistent launch per stage,
-eager and replayed from a HIP graph, each y_i against the oracle."""
+"""Batched path: many uneven matrices in one launch per stage (stage 1 as
+one wavefront per thread-bunch, or as a persistent grid), eager and replayed
+from a HIP graph, each y_i against the oracle."""
 import numpy as np
 import pytest
 
@@ -45,13 +46,35 @@ def to_dev(torch, mats, dtype):
     return out
 
 
+@pytest.mark.parametrize("persistent", [False, True])
 @pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
-def test_batched_integer_exact(torch_cuda, WS):
+def test_batched_integer_exact(torch_cuda, WS, persistent):
     torch = torch_cuda
     from paper_1504_06474_amd import sss
     mats = batch_set(True)
     dev = to_dev(torch, mats, torch.float64)
-    plan = sss.BatchPlan(dev, W=WS[0], S=WS[1])
+    plan = sss.BatchPlan(dev, W=WS[0], S=WS[1], persistent=persistent)
+    plan.execute()
+    torch.cuda.synchronize()
+    for (A, x), d in zip(mats, dev):
+        assert_exact(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("bunches", [1, 3, 17, 33])
+def test_batched_small_grids(torch_cuda, bunches, persistent):
+    """Batches of 1, 3, 17 and 33 thread-bunches (W = 8, S = 5, B = 2): stage
+    1's grid below 8 workgroups, and rounded up to a multiple of 8 with idle
+    wavefronts in the last workgroups; the last bunch is ragged."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    nnz = 2560 * bunches - 7
+    lengths = [10] * (nnz // 10) + ([nnz % 10] if nnz % 10 else [])
+    mats = [csr_from_lengths(lengths, 64, seed=700 + bunches, int_valued=True),
+            csr_from_lengths([0] * 5 + [3, 0, 2], 9, seed=800 + bunches, int_valued=True)]
+    dev = to_dev(torch, mats, torch.float64)
+    plan = sss.BatchPlan(dev, W=8, S=5, B=2, persistent=persistent)
+    assert plan.info()["n_bunches"] == bunches + 1
     plan.execute()
     torch.cuda.synchronize()
     for (A, x), d in zip(mats, dev):
@@ -142,17 +165,18 @@ def _full_set():
     return _FULL["mats"], _FULL["refs"]
 
 
-@pytest.mark.parametrize("kind", ["f64", "f32"])
-def test_batched_full_size_exact(torch_cuda, kind):
+@pytest.mark.parametrize("kind,persistent", [("f64", False), ("f32", False), ("f64", True)])
+def test_batched_full_size_exact(torch_cuda, kind, persistent):
     """All 512 matrices in the launch configuration the benchmark times (the
-    per-dtype default W, S), eager and then replayed from the captured graph
-    with y clobbered in between: every row of every matrix bit-exact."""
+    per-dtype default W, S; also the persistent stage 1 in FP64), eager and
+    then replayed from the captured graph with y clobbered in between: every
+    row of every matrix bit-exact."""
     torch = torch_cuda
     from paper_1504_06474_amd import sss
     tdt = torch.float64 if kind == "f64" else torch.float32
     mats, refs = _full_set()
     dev = to_dev(torch, mats, tdt)
-    plan = sss.BatchPlan(dev, dtype=tdt)
+    plan = sss.BatchPlan(dev, dtype=tdt, persistent=persistent)
     note(f"  {kind} batch plan {plan.info()}")
     plan.execute()
     torch.cuda.synchronize()
