@@ -154,11 +154,20 @@ int sss_csr_spmv_stage2_host(sss_plan p, const int32_t *row_ptr, void *y);
  * default parameters.  Keeps an internal plan per (device, stream, m, n, nnz)
  * that it allocates on first use (so the first call for a new size on a
  * stream is not graph-capturable; later calls are) and keeps until the
- * process ends.  Calls on one stream run in order; calls of the same size on
+ * process ends or sss_csr_spmv_cache_clear.  Calls on one stream run in
+ * order; calls of the same size on
  * different streams use different plans and may overlap. */
 int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                  const int32_t *col, const double *val, const double *x, double *y,
                  void *stream);
+
+/* Free every plan sss_csr_spmv has cached, on every device and stream (a
+ * process that sees many sizes can bound its memory this way).  Waits for
+ * the devices the plans live on; the next sss_csr_spmv of a size plans it
+ * again.  Must not run while another thread is inside sss_csr_spmv or while
+ * a stream is capturing one of its calls.  Returns the first error met, after
+ * freeing what it could. */
+int sss_csr_spmv_cache_clear(void);
 
 /* One matrix of a batch: device pointers (caller-owned, as for execute), its
  * sizes, and optionally its own S (tiles per wavefront; 0 = the batch's). */

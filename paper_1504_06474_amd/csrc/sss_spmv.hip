@@ -1380,6 +1380,23 @@ int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, cons
   return launch(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
 }
 
+int sss_csr_spmv_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (g_cache.empty()) return SSS_OK;
+  int rc = SSS_OK, cur = -1;
+  const hipError_t eg = hipGetDevice(&cur);
+  for (auto &kv : g_cache) {
+    // each plan is destroyed with its own device current
+    hipError_t e = hipSetDevice(kv.second->device);
+    int r = e == hipSuccess ? sss_plan_destroy(kv.second) : SSS_ERR_HIP;
+    if (e != hipSuccess) g_last_hip = e;
+    if (rc == SSS_OK) rc = r;
+  }
+  g_cache.clear();
+  if (eg == hipSuccess && cur >= 0) (void)hipSetDevice(cur);
+  return rc;
+}
+
 int sss_csr_spmv_stage2_host(sss_plan p, const int32_t *row_ptr, void *y) {
   if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
   if (p->m == 0 || p->nnz == 0) return SSS_OK;

@@ -100,7 +100,8 @@ def lib():
         L.sss_status_string.restype = ctypes.c_char_p
         L.sss_last_hip_error.restype = ctypes.c_char_p
         L.sss_version.restype = ctypes.c_char_p
-        for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_plan_destroy",
+        for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_csr_spmv_cache_clear",
+                  "sss_plan_destroy",
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
@@ -433,6 +434,11 @@ def csr_spmv(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: tor
     rc = lib().sss_csr_spmv(m, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y), _stream(stream))
     _check(rc, "sss_csr_spmv")
     return y
+
+
+def csr_spmv_cache_clear():
+    """Free the plans csr_spmv (sss_csr_spmv) has cached."""
+    _check(lib().sss_csr_spmv_cache_clear(), "sss_csr_spmv_cache_clear")
 
 
 def validate_csr(row_ptr: torch.Tensor, col: torch.Tensor, n: int, stream=None) -> bool:

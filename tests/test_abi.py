@@ -31,6 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings_and_version():
     from paper_1504_06474_amd import sss
     L = sss.lib()
+    assert L.sss_csr_spmv_cache_clear() == 0  # nothing cached: no device call
     assert L.sss_status_string(0) == b"ok"
     assert L.sss_status_string(-5) == b"malformed CSR matrix"
     assert b"gfx950" in L.sss_version()

@@ -170,6 +170,15 @@ def test_one_call_form_and_validate(torch_cuda):
     y2 = sss.csr_spmv(rp, col, v, xx)  # cached plan
     assert_exact(y.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
     assert torch.equal(y, y2)
+    # a second size, then the cache freed and both sizes planned again
+    A2, x2 = csrgen.config1(int_valued=True, m=700)
+    d2 = to_dev(A2, x2)
+    y3 = sss.csr_spmv(*d2)
+    sss.csr_spmv_cache_clear()
+    sss.csr_spmv_cache_clear()  # an empty cache is fine
+    assert torch.equal(sss.csr_spmv(rp, col, v, xx), y)
+    assert torch.equal(sss.csr_spmv(*d2), y3)
+    assert_exact(y3.cpu().numpy(), oracle.spmv(A2.row_ptr, A2.col, A2.val, x2))
     assert sss.validate_csr(rp, col, A.n)
     bad_col = col.clone()
     bad_col[5] = A.n
