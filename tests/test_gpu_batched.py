@@ -133,6 +133,32 @@ def test_batched_f32(torch_cuda):
         assert_exact(d[4].double().cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_bf16(torch_cuda, persistent):
+    """BF16 values (x and y FP32): integer values and x in {-3..3} are exact in
+    BF16 and every partial sum is exact in FP32, so each y_i is bit-exact;
+    both stage-1 forms, eager and replayed."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    from helpers import to_dev_precision
+    mats = batch_set(True)
+    dev, refs = [], []
+    for A, x in mats:
+        rp, col, v, xx, ve, xe = to_dev_precision(A, x, "bf16")
+        dev.append((rp, col, v, xx, torch.full((A.m,), float("nan"), dtype=torch.float32, device="cuda"), A.n))
+        refs.append(oracle.spmv(A.row_ptr, A.col, ve, xe))
+    plan = sss.BatchPlan(dev, dtype=torch.bfloat16, persistent=persistent)
+    for launch in (plan.execute, plan.graph_launch):
+        for d in dev:
+            d[4].fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        for d, ref in zip(dev, refs):
+            assert_exact(d[4].double().cpu().numpy(), ref)
+    plan.close()
+
+
 def test_batched_rejects_bad_descriptors(torch_cuda):
     torch = torch_cuda
     from paper_1504_06474_amd import sss
