@@ -733,7 +733,6 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
   stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.y);
 }
 
-
 // The same work as a persistent grid (batch_persistent plans): as many
 // workgroups as stay resident, a multiple of G; the workgroups with
 // blockIdx.x mod G = k stride over the k-th contiguous G-th of the global
