@@ -1,14 +1,17 @@
 """Seeded random matrices against the oracle, bit-exact (integer values and x
 in {-3..3}): row-length mixes that stress the method's corner cases -- runs of
 empty rows, rows spanning many thread-bunches, rows ending exactly on tile
-boundaries -- under random (W, S, B), searched or bound first rows, and
-random batches with per-matrix S."""
+boundaries -- under random (W, S, B), searched or bound first rows, FP64,
+FP32 or BF16 values, and random batches with per-matrix S in either stage-1
+form.  Integer values and x in {-3..3} are exact in BF16, and every partial
+sum (|s| <= 9 * 40 * 1024 < 2^24) is exact in FP32, so every type is
+compared bit for bit."""
 import numpy as np
 import pytest
 
 import csrgen
 import oracle
-from helpers import note, to_dev, assert_exact
+from helpers import note, to_dev, to_dev_precision, assert_exact
 
 pytestmark = pytest.mark.gpu
 
@@ -57,14 +60,15 @@ def test_fuzz_single(seed):
     S = int(rng.integers(1, 17))
     B = int(rng.integers(1, 5))
     bind = bool(rng.integers(0, 2))
+    kind = ("f64", "f32", "bf16")[int(rng.integers(0, 3))]
     A, x = random_matrix(seed, W)
-    note(f"  seed={seed} m={A.m} n={A.n} nnz={A.nnz} W={W} S={S} B={B} bind={bind}")
-    rp, col, v, xx = to_dev(A, x)
-    plan = sss.Plan(A.m, A.n, A.nnz, W=W, S=S, B=B, bind_rows=bind, row_ptr=rp if bind else None)
-    y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+    note(f"  seed={seed} m={A.m} n={A.n} nnz={A.nnz} W={W} S={S} B={B} bind={bind} {kind}")
+    rp, col, v, xx, ve, xe = to_dev_precision(A, x, kind)
+    plan = sss.Plan(A.m, A.n, A.nnz, dtype=v.dtype, W=W, S=S, B=B, bind_rows=bind, row_ptr=rp if bind else None)
+    y = torch.full((A.m,), float("nan"), dtype=xx.dtype, device="cuda")
     plan.execute(rp, col, v, xx, y)
     torch.cuda.synchronize()
-    assert_exact(y.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+    assert_exact(y.double().cpu().numpy(), oracle.spmv(A.row_ptr, A.col, ve, xe))
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -80,8 +84,9 @@ def test_fuzz_batched(seed):
         y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
         descs.append({"row_ptr": rp, "col": col, "val": v, "x": xx, "y": y, "n": A.n, "S": int(rng.integers(1, 17))})
         refs.append(oracle.spmv(A.row_ptr, A.col, A.val, x))
-    note(f"  seed={seed} matrices={len(mats)} W={W} nnz={sum(A.nnz for A, _ in mats)}")
-    plan = sss.BatchPlan(descs, W=W)
+    persistent = bool(rng.integers(0, 2))
+    note(f"  seed={seed} matrices={len(mats)} W={W} nnz={sum(A.nnz for A, _ in mats)} persistent={persistent}")
+    plan = sss.BatchPlan(descs, W=W, persistent=persistent)
     plan.execute()
     torch.cuda.synchronize()
     for d, ref in zip(descs, refs):
