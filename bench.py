@@ -414,6 +414,13 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
         info = bp.info()
         ms_batch = timed(bp.execute, steps)
         ms_graph = timed(bp.graph_launch, steps)
+        # memory floors of the batched stage 1's access pattern (same launch,
+        # the probe's loads in place of the method's work)
+        fo = torch.empty(info["n_bunches"] * 64, dtype=tdt, device="cuda")
+        bfl = {}
+        for name, gather in (("stream_us", False), ("stream_gather_us", True)):
+            bfl[name] = round(timed(lambda: bp.floor_probe(fo, gather), steps) * 1e3, 1)
+        del fo
         # the same plan with a persistent stage 1 (batch_persistent)
         bp_p = sss.BatchPlan(dev, dtype=tdt, persistent=True)
         ms_persistent = timed(bp_p.execute, steps)
@@ -459,6 +466,7 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
         out[kind] = {"W": info["W"], "S": info["S"], "n_bunches": info["n_bunches"],
                      "batched_us": round(ms_batch * 1e3, 1), "batched_graph_us": round(ms_graph * 1e3, 1),
                      "persistent_stage1_us": round(ms_persistent * 1e3, 1),
+                     "floors": bfl,
                      "separate_us": round(ms_sep * 1e3, 1), "separate_graph_us": round(ms_sep_graph * 1e3, 1),
                      "speedup_vs_separate": round(ms_sep / ms_batch, 2),
                      "speedup_vs_separate_graph": round(ms_sep_graph / ms_batch, 2),

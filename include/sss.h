@@ -299,6 +299,16 @@ const char *sss_rowwise_last_hip_error(void);
 int sss_floor_probe(sss_plan p, const int32_t *col, const void *val, const void *x, void *out, int gather,
                     void *stream);
 
+/* The same measurement for a batch plan: the batched stage 1's launch (one
+ * wavefront per thread-bunch, the same mapping of workgroups to XCDs and
+ * the same per-bunch lookup of matrix and bunch) running the probe's loads
+ * on each matrix's own col, val and x from the plan's descriptors.  out
+ * (device, y type of the plan) holds 64 elements per global thread-bunch:
+ * out[g*64 + lane] for bunch g of the concatenated bunch space
+ * (n_bunches from sss_plan_info).  SSS_ERR_UNSUPPORTED for a
+ * batch_persistent plan.  Asynchronous on `stream`. */
+int sss_batch_floor_probe(sss_plan p, void *out, int gather, void *stream);
+
 /* GRID-mode plan (the selector's fallback, and the yardstick of its regret):
  * runs sss_csr_spmv_autotune on the caller's matrix and returns in *out a
  * plan with the fastest class's (W, S), the default B and the rows bound

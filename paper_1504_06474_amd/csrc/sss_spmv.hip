@@ -651,14 +651,11 @@ __global__ void sss_batch_bunch_info(const MatCtx *__restrict__ mats, const int6
 // partial stores: each lane sums its products (GATHER) or its values plus
 // columns (stream only) and writes one value, so the loads cannot be dropped.
 template <int DT, int W, bool GATHER>
-__global__ __launch_bounds__(256) void sss_floor(MatCtx a, typename VT<DT>::y_t *__restrict__ out) {
+__device__ __forceinline__ double floor_bunch(const MatCtx &a, const int64_t tb, const int lane) {
   using val_t = typename VT<DT>::val_t;
   using x_t = typename VT<DT>::x_t;
   using prod_t = typename VT<DT>::prod_t;
   constexpr int WT = W * kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (tb >= a.n_bunches) return;
   const int32_t *__restrict__ col = a.col;
   const val_t *__restrict__ val = static_cast<const val_t *>(a.val);
   const x_t *__restrict__ x = static_cast<const x_t *>(a.x);
@@ -684,7 +681,15 @@ __global__ __launch_bounds__(256) void sss_floor(MatCtx a, typename VT<DT>::y_t 
       for (int i = 0; i < W; ++i) { xv[i] = GATHER ? (prod_t)x[cn[i]] : (prod_t)cn[i]; av[i] = an[i]; }
     }
   }
-  out[tb * kWave + lane] = (typename VT<DT>::y_t)acc;
+  return acc;
+}
+
+template <int DT, int W, bool GATHER>
+__global__ __launch_bounds__(256) void sss_floor(MatCtx a, typename VT<DT>::y_t *__restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (tb >= a.n_bunches) return;
+  out[tb * kWave + lane] = (typename VT<DT>::y_t)floor_bunch<DT, W, GATHER>(a, tb, lane);
 }
 
 // Many matrices in one launch per stage: the thread-bunches of all matrices
@@ -753,6 +758,24 @@ __global__ __launch_bounds__(256) void sss_stage1_batch_persistent(BatchArgs b) 
     const MatCtx a = b.mats[bi.x];
     stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.y);
   }
+}
+
+// Measurement aid for the batched stage 1: its launch (one wavefront per
+// bunch, the same XCD-contiguous mapping and the same per-bunch lookup) with
+// floor_bunch in place of the method's work; out has 64 entries per global
+// bunch.
+template <int DT, int W, bool GATHER>
+__global__ __launch_bounds__(256) void sss_floor_batch(BatchArgs b, typename VT<DT>::y_t *__restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int G = min((int)gridDim.x, kXcds);
+  const int64_t per = gridDim.x / G;
+  const int64_t wg = (int64_t)(blockIdx.x % G) * per + blockIdx.x / G;
+  const int64_t g = wg * (blockDim.x / kWave) + wid;
+  if (g >= b.total_bunches) return;
+  const int4 bi = b.bunch_info[g];
+  const MatCtx a = b.mats[bi.x];
+  out[g * kWave + lane] = (typename VT<DT>::y_t)floor_bunch<DT, W, GATHER>(a, bi.z, lane);
 }
 
 // ---------------------------------------------------------------- stage 2
@@ -1207,6 +1230,29 @@ int launch_floor(sss_plan p, const MatCtx &a, void *out, int gather, hipStream_t
   return SSS_OK;
 }
 
+template <int DT, int W>
+int launch_floor_batch(sss_plan p, void *out, int gather, hipStream_t stream) {
+  using y_t = typename VT<DT>::y_t;
+  if (gather)
+    hipLaunchKernelGGL((sss_floor_batch<DT, W, true>), dim3((unsigned)p->blocks1), dim3(p->B * kWave), 0, stream,
+                       p->bargs, static_cast<y_t *>(out));
+  else
+    hipLaunchKernelGGL((sss_floor_batch<DT, W, false>), dim3((unsigned)p->blocks1), dim3(p->B * kWave), 0, stream,
+                       p->bargs, static_cast<y_t *>(out));
+  SSS_HIP(hipGetLastError());
+  return SSS_OK;
+}
+
+template <int DT>
+int launch_floor_batch_w(sss_plan p, void *out, int gather, hipStream_t stream) {
+  switch (p->W) {
+    case 4: return launch_floor_batch<DT, 4>(p, out, gather, stream);
+    case 8: return launch_floor_batch<DT, 8>(p, out, gather, stream);
+    case 16: return launch_floor_batch<DT, 16>(p, out, gather, stream);
+    default: return SSS_ERR_UNSUPPORTED;
+  }
+}
+
 template <int DT>
 int launch_floor_w(sss_plan p, const MatCtx &a, void *out, int gather, hipStream_t stream) {
   switch (p->W) {
@@ -1596,6 +1642,23 @@ int sss_batch_graph_launch(sss_plan p, void *stream) {
   }
   SSS_HIP(hipGraphLaunch(p->graph_exec, static_cast<hipStream_t>(stream)));
   return SSS_OK;
+}
+
+int sss_batch_floor_probe(sss_plan p, void *out, int gather, void *stream) {
+  if (!p || !p->batch) return SSS_ERR_INVALID_VALUE;
+  if (p->batch_persistent) return SSS_ERR_UNSUPPORTED;  // the probe mirrors the default launch
+  if (p->bargs.total_bunches == 0) return SSS_OK;
+  if (!out) return SSS_ERR_INVALID_VALUE;
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  switch (p->dt) {
+    case SSS_F64: return launch_floor_batch_w<SSS_F64>(p, out, gather, s);
+    case SSS_F32: return launch_floor_batch_w<SSS_F32>(p, out, gather, s);
+    case SSS_BF16: return launch_floor_batch_w<SSS_BF16>(p, out, gather, s);
+    default: return SSS_ERR_UNSUPPORTED;
+  }
 }
 
 int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t *n_bunches) {

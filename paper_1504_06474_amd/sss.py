@@ -73,6 +73,7 @@ def lib():
         L.sss_batch_plan_create.argtypes = [I, ctypes.POINTER(CsrDesc), I, ctypes.POINTER(PlanOpts), P,
                                             ctypes.POINTER(P)]
         L.sss_batch_execute.argtypes = [P, P]
+        L.sss_batch_floor_probe.argtypes = [P, P, I, P]
         FP = ctypes.POINTER(ctypes.c_float)
         L.sss_class_params.argtypes = [I, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
@@ -104,7 +105,7 @@ def lib():
                   "sss_plan_destroy",
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
-                  "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch",
+                  "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch", "sss_batch_floor_probe",
                   "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_csr_spmv_stage2_host", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
                   "sss_selector_loaded"):
@@ -311,6 +312,16 @@ class BatchPlan:
 
     def execute(self, stream=None):
         _check(lib().sss_batch_execute(self._h, _stream(stream)), "sss_batch_execute")
+
+    def floor_probe(self, out: torch.Tensor, gather: bool = True, stream=None) -> torch.Tensor:
+        """Memory floor of the batched stage 1's access pattern
+        (sss_batch_floor_probe): one sum per lane per global bunch in `out`
+        (n_bunches * 64 elements of the y type)."""
+        if out.numel() < self.info()["n_bunches"] * 64 or out.dtype != _XTYPE[self.dt]:
+            raise ValueError("out must hold n_bunches * 64 elements of the plan's y type")
+        _check(lib().sss_batch_floor_probe(self._h, _ptr(out), 1 if gather else 0, _stream(stream)),
+               "sss_batch_floor_probe")
+        return out
 
     def graph_launch(self, stream=None):
         _check(lib().sss_batch_graph_launch(self._h, _stream(stream)), "sss_batch_graph_launch")

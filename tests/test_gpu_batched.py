@@ -159,6 +159,29 @@ def test_batched_bf16(torch_cuda, persistent):
     plan.close()
 
 
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_batched_floor_probe_reads_every_nonzero_once(torch_cuda, kind):
+    """The batched measurement kernel streams exactly every matrix once: on
+    integer-valued data the sum of its outputs is the sum over all matrices of
+    sum_k val[k] * x[col[k]] (gather) and of sum_k (val[k] + col[k]) (stream
+    only), exactly; a persistent plan is refused."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    tdt = torch.float64 if kind == "f64" else torch.float32
+    mats = batch_set(True)
+    dev = to_dev(torch, mats, tdt)
+    plan = sss.BatchPlan(dev, dtype=tdt)
+    out = torch.full((plan.info()["n_bunches"] * 64,), float("nan"), dtype=tdt, device="cuda")
+    plan.floor_probe(out, gather=True)
+    torch.cuda.synchronize()
+    assert float(out.double().sum()) == float(sum(np.sum(A.val * x[A.col]) for A, x in mats))
+    plan.floor_probe(out, gather=False)
+    torch.cuda.synchronize()
+    assert float(out.double().sum()) == float(sum(np.sum(A.val + A.col) for A, x in mats))
+    with pytest.raises(sss.SSSError):
+        sss.BatchPlan(dev, dtype=tdt, persistent=True).floor_probe(out)
+
+
 def test_batched_rejects_bad_descriptors(torch_cuda):
     torch = torch_cuda
     from paper_1504_06474_amd import sss
