@@ -1,7 +1,8 @@
-"""bench.py reports its error figures against its own reference (`row_sums`:
-products and row sums in long double).  Here that reference is checked
-against the oracle: ragged rows, runs of empty rows at both ends, a long row,
-all-empty and nnz = 0 matrices."""
+"""bench.py on the CPU.  Its error figures use its own reference (`row_sums`:
+products and row sums in long double), checked here against the oracle:
+ragged rows, runs of empty rows at both ends, a long row, all-empty and
+nnz = 0 matrices.  Also: it refuses more than one GPU, and its JSON line
+holds no NaN or infinity."""
 import numpy as np
 
 import bench
@@ -41,3 +42,24 @@ def test_row_sums_degenerate():
     rp = np.array([0, 0, 2, 2, 3], np.int32)
     y, sc = bench.row_sums(rp, np.array([0, 2, 1], np.int32), np.array([2.0, -1.0, 4.0]), x)
     assert list(y) == [0.0, -1.0, 0.0, -8.0] and list(sc) == [0.0, 5.0, 0.0, 8.0]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says so,
+    before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_bench_json_has_no_non_finite_numbers():
+    import json
+    line = json.dumps(bench._finite({"a": float("nan"), "b": [1.5, float("-inf")], "c": {"d": float("inf")}}),
+                      allow_nan=False)
+    assert json.loads(line) == {"a": None, "b": [1.5, None], "c": {"d": None}}
