@@ -161,6 +161,38 @@ def test_repeat_and_determinism(torch_cuda):
         assert np.array_equal(y, ys[0])
 
 
+def test_plans_on_two_streams(torch_cuda):
+    """Two plans on two streams (default priority), launches interleaved, and
+    the one-call form of one size on both streams (a cached plan per
+    stream): no hidden state is shared, every result exact."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A1, x1 = csrgen.config1(int_valued=True)
+    A2, x2 = csrgen.config1(int_valued=True, m=3000)
+    d1, d2 = to_dev(A1, x1), to_dev(A2, x2)
+    p1 = sss.Plan(A1.m, A1.n, A1.nnz, bind_rows=True, row_ptr=d1[0])
+    p2 = sss.Plan(A2.m, A2.n, A2.nnz, W=4, S=3)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    y1 = torch.empty(A1.m, dtype=torch.float64, device="cuda")
+    y2 = torch.empty(A2.m, dtype=torch.float64, device="cuda")
+    ya = torch.empty(A1.m, dtype=torch.float64, device="cuda")
+    yb = torch.empty(A1.m, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(20):
+        p1.execute(*d1, y1, stream=s1)
+        p2.execute(*d2, y2, stream=s2)
+        sss.csr_spmv(*d1, y=ya, stream=s1)
+        sss.csr_spmv(*d1, y=yb, stream=s2)
+    torch.cuda.synchronize()
+    ref1 = oracle.spmv(A1.row_ptr, A1.col, A1.val, x1)
+    assert_exact(y1.cpu().numpy(), ref1)
+    assert_exact(y2.cpu().numpy(), oracle.spmv(A2.row_ptr, A2.col, A2.val, x2))
+    assert_exact(ya.cpu().numpy(), ref1)
+    assert_exact(yb.cpu().numpy(), ref1)
+    p1.close()
+    p2.close()
+
+
 def test_one_call_form_and_validate(torch_cuda):
     torch = torch_cuda
     from paper_1504_06474_amd import sss
