@@ -69,3 +69,12 @@ def test_host_side_argument_checks():
     assert L.sss_csr_spmv_plan_create(10, 10, big + 1, None, 0, None, None, ctypes.byref(h)) == -1
     assert L.sss_csr_spmv_plan_create(10, big + 1, 10, None, 0, None, None, ctypes.byref(h)) == -1
     assert "#define SSS_MAX_INDEX 2147479551" in open(os.path.join(ROOT, "include", "sss.h")).read()
+    # calls on a NULL plan are rejected before any device call
+    assert L.sss_batch_execute(None, None) == -1
+    assert L.sss_batch_graph_launch(None, None) == -1
+    assert L.sss_batch_floor_probe(None, None, 1, None) == -1
+    assert L.sss_floor_probe(None, None, None, None, None, 1, None) == -1
+    assert L.sss_csr_spmv_stage1(None, None, None, None, None, None, None) == -1
+    assert L.sss_csr_spmv_stage2(None, None, None, None) == -1
+    assert L.sss_csr_spmv_stage2_host(None, None, None) == -1
+    assert L.sss_plan_destroy(None) == 0
