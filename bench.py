@@ -295,7 +295,10 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
             rec.setdefault("err_vs_f64", {})[values] = error_stats(yh, ref64, sc64)
             if kind != "f64":
                 refq, scq = row_sums(Av.row_ptr, Av.col, ve, xe)
-                rec.setdefault("err_arith_only", {})[values] = error_stats(yh, refq, scq)
+                st = error_stats(yh, refq, scq)
+                # in units of u = 2^-24: products rounded once and y rounded once give at most 2
+                st["max_scaled_in_u"] = round(st["max_scaled"] / 2.0 ** -24, 4)
+                rec.setdefault("err_arith_only", {})[values] = st
             del rp, col, v, xx, y
             plan.close()
             log(f"[bench] precision {values} {kind}: {rec.get('us')} us")

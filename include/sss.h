@@ -21,9 +21,10 @@
  *   All matrix and vector pointers passed to execute calls are caller-owned
  *   DEVICE pointers on the current HIP device; the library never frees or
  *   retains them past the call.  col and val must be 16-byte aligned (any
- *   hipMalloc / PyTorch allocation is).  A plan owns its auxiliary device
- *   buffers (synchronizer, per-bunch dirty masks, speculator) from create to
- *   destroy.
+ *   hipMalloc / PyTorch allocation is).  A plan's auxiliary device arrays
+ *   (synchronizer, bunch tails, per-bunch dirty masks, speculator) live
+ *   from create to destroy, in its own allocation or in a workspace the
+ *   caller provides (e.g. a PyTorch tensor).
  *   y is overwritten (not accumulated into).
  *
  * Streams
@@ -50,7 +51,7 @@ typedef enum {
   SSS_OK = 0,
   SSS_ERR_INVALID_VALUE = -1,  /* negative size, null pointer with nonzero size, bad option, misaligned */
   SSS_ERR_UNSUPPORTED = -2,    /* dtype or parameter combination not built */
-  SSS_ERR_PLAN_MISMATCH = -3,  /* plan used with sizes or dtype it was not made for */
+  SSS_ERR_PLAN_MISMATCH = -3,  /* plan used on another device, or a bind_rows plan with another row_ptr */
   SSS_ERR_HIP = -4,            /* a HIP runtime call failed */
   SSS_ERR_INVALID_CSR = -5     /* sss_validate_csr found a malformed matrix */
 } sss_status;
@@ -92,36 +93,62 @@ typedef struct {
   int bind_rows; /* nonzero: plan_create runs the tile boundary search of
                     Section 3.2 once, for every thread-bunch's first row, on
                     row_ptr (required); execute then reads those rows instead
-                    of searching, and the plan serves only matrices whose
-                    row_ptr has the same contents */
+                    of searching; the plan then serves only that row_ptr
+                    array (SSS_ERR_PLAN_MISMATCH for another) */
   int batch_persistent; /* batch plans only.  0 (default): stage 1 launches one
                            wavefront per thread-bunch of every matrix.  Nonzero:
                            stage 1 is a persistent grid (as many workgroups as
                            stay resident) whose wavefronts loop over the
                            bunches.  Same results; the default measured faster. */
+  void *workspace;        /* single-matrix plans: caller-owned DEVICE memory for the
+                             plan's auxiliary arrays, 256-byte aligned, at least
+                             sss_csr_spmv_plan_workspace_size bytes, kept alive and
+                             unused by others until sss_plan_destroy.  NULL: the
+                             plan allocates its own (hipMalloc) and frees it. */
+  size_t workspace_bytes; /* size of `workspace` (0 when it is NULL) */
 } sss_plan_opts;
 
 typedef struct sss_plan_s *sss_plan;
 
 /* Create a plan for an m x n matrix with nnz nonzeros of value type dt.
- * Section 3.3 sizes the auxiliary arrays it allocates: the synchronizer has
- * one entry per thread-bunch, ceil(nnz / (S W T)); the speculator one per
- * tile, ceil(nnz / (W T)), here laid out as S slots per thread-bunch with a
- * per-bunch dirty mask in place of the single global dirty counter.
- * m, n and nnz must not exceed SSS_MAX_INDEX (else SSS_ERR_INVALID_VALUE).
- * row_ptr (device, may be NULL in FIXED mode without bind_rows) is read only
- * by the SELECTOR mode and by bind_rows, on `stream`, which this call then
- * synchronises.
- * opts may be NULL (FIXED with the defaults).  Returns the plan in *out. */
+ * Section 3.3 sizes the auxiliary arrays it holds: the synchronizer has one
+ * entry per thread-bunch, ceil(nnz / (S W T)); the speculator one per tile,
+ * ceil(nnz / (W T)), here laid out as S slots per thread-bunch with a
+ * per-bunch dirty mask in place of the single global dirty counter; beside
+ * the synchronizer each bunch keeps its tail (the part of the row it ends
+ * in, when that row goes on into the next bunch) in double, so that a row's
+ * parts from several bunches meet in double and y is rounded once.
+ * The arrays live in opts->workspace when given (nothing is allocated), else
+ * in one hipMalloc owned by the plan.  They are cleared on `stream`.
+ * m, n and nnz must not exceed SSS_MAX_INDEX (else SSS_ERR_INVALID_VALUE);
+ * a workspace that is too small or not 256-byte aligned is
+ * SSS_ERR_INVALID_VALUE.  row_ptr (device, may be NULL in FIXED mode without
+ * bind_rows) is read only by the SELECTOR mode and by bind_rows.  Work is
+ * enqueued on `stream`, which this call synchronises before it returns (no
+ * device-wide synchronisation).  opts may be NULL (FIXED with the defaults).
+ * Returns the plan in *out. */
 int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                              sss_dtype dt, const sss_plan_opts *opts, void *stream,
                              sss_plan *out);
+
+/* Bytes of device workspace a plan with these arguments needs (host call, no
+ * device work): FIXED mode the exact size for its (W, S); SELECTOR mode the
+ * largest over the parameter grid and the type's defaults, since the choice
+ * is made in plan_create.  opts->workspace is ignored.  SSS_ERR_INVALID_VALUE
+ * / SSS_ERR_UNSUPPORTED as for plan_create. */
+int sss_csr_spmv_plan_workspace_size(int64_t m, int64_t n, int64_t nnz, sss_dtype dt,
+                                     const sss_plan_opts *opts, size_t *bytes);
 
 /* y = A x with a plan (both stages of Section 3.2, enqueued on `stream`).
  * The sizes are the plan's; val/x/y types follow the plan's dtype.  m = 0 is a
  * no-op; nnz = 0 zeroes y.  SSS_ERR_INVALID_VALUE for a NULL plan, a NULL
  * pointer whose array is non-empty, or misaligned col/val.  SSS_ERR_PLAN_MISMATCH
- * if the plan was created on another device. */
+ * if the plan was created on another device, or if it binds rows (bind_rows)
+ * and row_ptr is not the array it was made for.  A bound plan's stage 1 also
+ * checks each thread-bunch's stored first row against row_ptr's contents
+ * (rp[r] <= b < rp[r + 1]) and searches again where it no longer holds, so
+ * rewriting that array in place (same m and nnz) gives a correct y, at the
+ * search's cost. */
 int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col,
                          const void *val, const void *x, void *y, void *stream);
 
@@ -216,7 +243,9 @@ int sss_batch_execute(sss_plan p, void *stream);
  * on a private stream) and replayed on `stream` by every call. */
 int sss_batch_graph_launch(sss_plan p, void *stream);
 
-/* Free a plan's device buffers (synchronises the device first). NULL is OK. */
+/* Free a plan.  Its own device buffer (no workspace given) goes with hipFree,
+ * which waits for the device's outstanding work; a caller-provided workspace
+ * is left to the caller and nothing waits.  NULL is OK. */
 int sss_plan_destroy(sss_plan p);
 
 /* The plan's chosen parameters and sizes (host integers, any may be NULL). */
@@ -243,7 +272,11 @@ int sss_plan_debug_size(sss_plan p, size_t *bytes);
  *          tile, in tile order; the first dirty_count entries are valid
  *   int32 sync_idx[n_bunches]
  *   double sync_val[n_bunches]
- * Section 3.2 and the appendix algorithm define these arrays. */
+ *   double tail_val[n_bunches]         the bunch's last partial where it ends
+ *          inside a row that is not its first row and continues into the
+ *          next bunch (else the value a previous call left, or 0)
+ * Section 3.2 and the appendix algorithm define these arrays (the tail is
+ * this implementation's: the paper stores that partial to y). */
 int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes);
 
 /* ---------------------------------------------------------------------------

@@ -82,6 +82,13 @@ __global__ __launch_bounds__(kFeatThreads) void sss_row_stats(const int32_t *__r
   }
 }
 
+// The per-block partial statistics: one array per device in the code object
+// (no allocation per call); calls are serialised by a mutex and each waits
+// for its stream before it returns.
+__device__ double feat_part[4 * kFeatBlocks];
+std::mutex g_feat_mu;
+double *g_feat_ptr[64] = {};
+
 // ---------------------------------------------------------------- network
 
 // Y[n][o] = act(sum_i X[n][i] W[i][o] + b[o]); one thread per output.
@@ -249,14 +256,21 @@ int sss_csr_features(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, 
   double sum = 0, sq = 0, mx = 0, em = 0;
   if (m > 0) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double *d_part = nullptr;
-    SEL_HIP(hipMalloc(&d_part, sizeof(double) * 4 * kFeatBlocks));
+    int dev = 0;
+    SEL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return SSS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_feat_mu);
+    if (!g_feat_ptr[dev]) {
+      void *ptr = nullptr;
+      SEL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(feat_part)));
+      g_feat_ptr[dev] = static_cast<double *>(ptr);
+    }
+    double *d_part = g_feat_ptr[dev];
     std::vector<double> part(4 * kFeatBlocks);
     hipLaunchKernelGGL(sss_row_stats, dim3(kFeatBlocks), dim3(kFeatThreads), 0, s, row_ptr, m, d_part);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(part.data(), d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d_part);
     if (e != hipSuccess) { g_sel_hip = e; return SSS_ERR_HIP; }
     for (int b = 0; b < kFeatBlocks; ++b) {
       sum += part[4 * b];

@@ -349,6 +349,8 @@ struct MatCtx {
   int4 *speculator;      // per bunch, S slots: <start, stop, tile, 0> of its dirty tiles, packed
   int32_t *sync_idx;
   double *sync_val;
+  double *tail_val;      // per bunch: its last partial, when the bunch ends inside a row that is not
+                         // its first row and continues into the next bunch (written only then)
   const int32_t *bunch_row;  // per bunch: its first row, found at plan time (NULL: search)
   int32_t *dbg_start;    // debug plans only
   int32_t *dbg_dirty;
@@ -410,8 +412,10 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
   load_tile<W>(col, val, b0, nnz, lane, cc, av);
 
   // ---- tile boundary search (rightmost match) for the bunch's first row,
-  // unless the plan found it once for all calls
-  const int r0 = r0_known >= 0 ? r0_known : wave_rightmost(rp, m, b0, lane);
+  // unless the plan found it once for all calls; such a row is checked in the
+  // row pass below
+  int r0 = r0_known >= 0 ? r0_known : wave_rightmost(rp, m, b0, lane);
+  bool verify = r0_known >= 0;
 
   // ---- x gathers of tile 0: they need only the columns, so they go out
   // before the row pass and travel with its loads
@@ -431,6 +435,18 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     const int r = rbase + lane;
     const int p = (r <= m) ? rp[r] : INT_MAX;
     const int q = (r < m) ? rp[r + 1] : INT_MAX;
+    if (verify) {
+      // a row found at plan time is the rightmost match of b0 exactly when
+      // rp[r0] <= b0 < rp[r0 + 1]; if row_ptr no longer says so, search
+      // (the pass has accumulated nothing yet)
+      verify = false;
+      const int p0 = __shfl(p, 0, kWave), q0 = __shfl(q, 0, kWave);
+      if (!(p0 <= b0 && b0 < q0)) {
+        r0 = wave_rightmost(rp, m, b0, lane);
+        rbase = r0 - kWave;
+        continue;
+      }
+    }
     if (r < m && q > p && p >= b0 && p < bS) {
       const int off = p - b0;
       atomicOr(&mask[off >> 5], 1u << (off & 31));
@@ -555,19 +571,24 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     }
     __builtin_amdgcn_wave_barrier();
 
-    // ---- coalesced store of the compact partials to y[start + q]; the
-    // bunch's first segment goes to the synchronizer; a tile that ends inside
-    // row `stop` writes its last partial at y[stop] and transmits it
+    // ---- coalesced store of the compact partials to y[start + q].  Two
+    // partials stay in double instead: the bunch's first segment goes to the
+    // synchronizer, and the last partial of a tile that ends inside row
+    // `stop` is not stored -- it travels on in the transmitter to the next
+    // tile of the bunch, which stores the row's sum, or, after the bunch's
+    // last tile, to the bunch's tail, which stage 2 adds to the row's
+    // carries before the row's only rounding to y's type.
     for (int q = lane; q < cnt; q += kWave) {
-      const double pv = part[q];
       const bool last = (q == cnt - 1);
-      const int idx = (last && ends_mid) ? stop : start + q;
-      if (!(q == 0 && start == r0) && (unsigned)idx < (unsigned)m) y_store((y_t)pv, &y[idx]);
+      const int idx = start + q;
+      if (!(q == 0 && start == r0) && !(last && ends_mid) && (unsigned)idx < (unsigned)m)
+        y_store((y_t)part[q], &y[idx]);
     }
     const double p0 = part[0];
     const double plast = part[cnt - 1];
     if (start == r0) sync_v = p0;
     transmitter = ends_mid ? plast : 0.0;
+    if (!has_next && ends_mid && !(cnt == 1 && start == r0) && lane == 0) a.tail_val[tb] = plast;
     __builtin_amdgcn_wave_barrier();
 
     // ---- dirty tile: label it for the re-arrangement, in this bunch's own
@@ -834,13 +855,15 @@ __device__ __forceinline__ void fixup_dirty(const MatCtx &a, const int64_t tb, Y
 }
 
 // (2) synchronizer carries for thread-bunches chunk0 .. chunk0+63 (one lane
-// each): for each run of bunches whose first row is the same row r, add their
-// first-segment sums to y[r], in double.  y[r] holds the part of r computed
-// before the run, unless row r begins exactly where the run's first bunch
-// begins.  Runs of up to kShortRun bunches are summed by the run's first lane
-// in bunch order; longer runs (rows longer than kShortRun bunches) by the
-// whole wavefront: coalesced loads, per-lane partial sums, then a fixed-shape
-// tree over the lanes, so the rounding does not depend on timing.
+// each): for each run of bunches whose first row is the same row r, sum their
+// first-segment sums in double and write y[r] once.  Unless row r begins
+// exactly where the run's first bunch begins, the part of r computed before
+// the run is the tail of the bunch before the run (double), added first; y[r]
+// is rounded to its type only here.  Runs of up to kShortRun bunches are
+// summed by the run's first lane in bunch order; longer runs (rows longer than
+// kShortRun bunches) by the whole wavefront: coalesced loads, per-lane partial
+// sums, then a fixed-shape tree over the lanes, so the rounding does not
+// depend on timing.
 template <typename YT>
 __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chunk0, const int lane) {
   const int32_t *__restrict__ rp = a.row_ptr;
@@ -884,7 +907,7 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
     for (int j = 0; j < kShortRun; ++j)
       if (idn[j] == idx) sum += vv[j];
     const bool fresh = (int64_t)rp[idx] == tb * SWT;
-    y[idx] = fresh ? (YT)sum : (YT)((double)y[idx] + sum);
+    y[idx] = (YT)(fresh ? sum : a.tail_val[tb - 1] + sum);
   }
   uint64_t longs = __ballot(is_long);
   while (longs) {
@@ -902,7 +925,7 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
     const double total = wave_sum_tree(acc);
     if (lane == l) {
       const bool fresh = (int64_t)rp[ridx] == t0 * SWT;
-      y[ridx] = fresh ? (YT)total : (YT)((double)y[ridx] + total);
+      y[ridx] = (YT)(fresh ? total : a.tail_val[t0 - 1] + total);
     }
   }
 }
@@ -1054,12 +1077,15 @@ struct sss_plan_s {
   int W = 8, S = 5, B = 2;
   int debug = 0;
   int bind_rows = 0;
+  const int32_t *bound_row_ptr = nullptr;  // bind_rows plans: the row_ptr they were made for
   int64_t n_tiles = 0, n_bunches = 0;
   void *aux = nullptr;
+  bool owns_aux = false;  // false: caller-provided workspace, or the static scratch
   uint32_t *dirty_mask = nullptr;
   int4 *speculator = nullptr;
   int32_t *sync_idx = nullptr;
   double *sync_val = nullptr;
+  double *tail_val = nullptr;
   int32_t *bunch_row = nullptr;  // plans made with bind_rows only
   int32_t *dbg_start = nullptr;
   int32_t *dbg_dirty = nullptr;
@@ -1078,39 +1104,69 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int plan_alloc(sss_plan p) {
-  const int WT = p->W * kWave;
-  p->n_tiles = p->nnz > 0 ? (p->nnz + WT - 1) / WT : 0;
-  const int64_t SWT = (int64_t)p->S * WT;
-  p->n_bunches = p->nnz > 0 ? (p->nnz + SWT - 1) / SWT : 0;
-  const int64_t nt = p->n_tiles, nb = p->n_bunches;
+// Byte offsets of a plan's auxiliary arrays in one device buffer (Section
+// 3.3 sizes them: one synchronizer entry per thread-bunch, one speculator
+// entry per tile), every array 256-byte aligned.
+struct AuxLayout {
+  int64_t n_tiles = 0, n_bunches = 0;
+  size_t dmask = 0, spec = 0, sidx = 0, sval = 0, tail = 0, brow = 0, dstart = 0, ddirty = 0, dheads = 0;
+  size_t total = 0;
+};
+
+AuxLayout aux_layout(int64_t nnz, int W, int S, bool bind, bool debug) {
+  AuxLayout L;
+  const int WT = W * kWave;
+  L.n_tiles = nnz > 0 ? (nnz + WT - 1) / WT : 0;
+  const int64_t SWT = (int64_t)S * WT;
+  L.n_bunches = nnz > 0 ? (nnz + SWT - 1) / SWT : 0;
+  const size_t nt = (size_t)L.n_tiles, nb = (size_t)L.n_bunches;
   size_t off = 0;
-  const size_t o_dmask = off; off = align256(off + sizeof(uint32_t) * (size_t)(nb + 1));
-  const size_t o_spec = off; off = align256(off + sizeof(int4) * (size_t)(nb * p->S + 1));
-  const size_t o_sidx = off; off = align256(off + sizeof(int32_t) * (size_t)(nb + 1));
-  const size_t o_sval = off; off = align256(off + sizeof(double) * (size_t)(nb + 1));
-  size_t o_br = 0;
-  if (p->bind_rows) { o_br = off; off = align256(off + sizeof(int32_t) * (size_t)(nb + 1)); }
-  size_t o_ds = 0, o_dd = 0, o_dh = 0;
-  if (p->debug) {
-    o_ds = off; off = align256(off + sizeof(int32_t) * (size_t)(nt + 1));
-    o_dd = off; off = align256(off + sizeof(int32_t) * (size_t)(nt + 1));
-    o_dh = off; off = align256(off + sizeof(uint32_t) * (size_t)(nt + 1) * (WT / 32));
+  L.dmask = off; off = align256(off + sizeof(uint32_t) * (nb + 1));
+  L.spec = off; off = align256(off + sizeof(int4) * (nb * (size_t)S + 1));
+  L.sidx = off; off = align256(off + sizeof(int32_t) * (nb + 1));
+  L.sval = off; off = align256(off + sizeof(double) * (nb + 1));
+  L.tail = off; off = align256(off + sizeof(double) * (nb + 1));
+  if (bind) { L.brow = off; off = align256(off + sizeof(int32_t) * (nb + 1)); }
+  if (debug) {
+    L.dstart = off; off = align256(off + sizeof(int32_t) * (nt + 1));
+    L.ddirty = off; off = align256(off + sizeof(int32_t) * (nt + 1));
+    L.dheads = off; off = align256(off + sizeof(uint32_t) * (nt + 1) * (size_t)(WT / 32));
   }
-  SSS_HIP(hipMalloc(&p->aux, off));
-  SSS_HIP(hipMemset(p->aux, 0, off));
-  char *base = static_cast<char *>(p->aux);
-  p->dirty_mask = reinterpret_cast<uint32_t *>(base + o_dmask);
-  p->speculator = reinterpret_cast<int4 *>(base + o_spec);
-  p->sync_idx = reinterpret_cast<int32_t *>(base + o_sidx);
-  p->sync_val = reinterpret_cast<double *>(base + o_sval);
-  if (p->bind_rows) p->bunch_row = reinterpret_cast<int32_t *>(base + o_br);
-  if (p->debug) {
-    p->dbg_start = reinterpret_cast<int32_t *>(base + o_ds);
-    p->dbg_dirty = reinterpret_cast<int32_t *>(base + o_dd);
-    p->dbg_heads = reinterpret_cast<uint32_t *>(base + o_dh);
+  L.total = off;
+  return L;
+}
+
+// Point the plan's arrays into `base` (a buffer of at least L.total bytes).
+void plan_bind_aux(sss_plan p, const AuxLayout &L, void *base_v) {
+  char *base = static_cast<char *>(base_v);
+  p->n_tiles = L.n_tiles;
+  p->n_bunches = L.n_bunches;
+  p->aux = base_v;
+  p->dirty_mask = reinterpret_cast<uint32_t *>(base + L.dmask);
+  p->speculator = reinterpret_cast<int4 *>(base + L.spec);
+  p->sync_idx = reinterpret_cast<int32_t *>(base + L.sidx);
+  p->sync_val = reinterpret_cast<double *>(base + L.sval);
+  p->tail_val = reinterpret_cast<double *>(base + L.tail);
+  p->bunch_row = p->bind_rows ? reinterpret_cast<int32_t *>(base + L.brow) : nullptr;
+  p->dbg_start = p->debug ? reinterpret_cast<int32_t *>(base + L.dstart) : nullptr;
+  p->dbg_dirty = p->debug ? reinterpret_cast<int32_t *>(base + L.ddirty) : nullptr;
+  p->dbg_heads = p->debug ? reinterpret_cast<uint32_t *>(base + L.dheads) : nullptr;
+}
+
+// The plan's auxiliary buffer: the caller's workspace when given (nothing is
+// allocated), else one hipMalloc owned by the plan.  Cleared on `stream`
+// (stream-ordered; the caller of plan_create synchronises that stream).
+int plan_alloc(sss_plan p, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+  const AuxLayout L = aux_layout(p->nnz, p->W, p->S, p->bind_rows != 0, p->debug != 0);
+  void *base = workspace;
+  if (workspace) {
+    if (workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u)) return SSS_ERR_INVALID_VALUE;
+  } else {
+    SSS_HIP(hipMalloc(&base, L.total));
+    p->owns_aux = true;
   }
-  SSS_HIP(hipDeviceSynchronize());
+  plan_bind_aux(p, L, base);
+  SSS_HIP(hipMemsetAsync(base, 0, L.total, stream));
   return SSS_OK;
 }
 
@@ -1123,10 +1179,28 @@ int check_call(sss_plan p, const int32_t *row_ptr, const int32_t *col, const voi
     if (!col || !val || !x) return SSS_ERR_INVALID_VALUE;
     if (misaligned(col) || misaligned(val)) return SSS_ERR_INVALID_VALUE;
   }
+  // a plan whose rows were bound at plan time serves the row_ptr it was made
+  // for (stage 1 also checks every bound row against row_ptr's contents and
+  // searches again where one no longer holds, so y stays right even if that
+  // array was rewritten in place)
+  if (p->bind_rows && row_ptr != p->bound_row_ptr) return SSS_ERR_PLAN_MISMATCH;
   int dev = -1;
   SSS_HIP(hipGetDevice(&dev));
   if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
   return SSS_OK;
+}
+
+// The kernels' view of a single-matrix plan and the caller's arrays.
+MatCtx plan_ctx(sss_plan p, const int32_t *row_ptr, const int32_t *col, const void *val, const void *x, void *y) {
+  MatCtx a{};
+  a.row_ptr = row_ptr; a.col = col; a.val = val; a.x = x; a.y = y;
+  a.m = (int32_t)p->m; a.nnz = (int32_t)p->nnz; a.S = p->S; a.W = p->W;
+  a.n_bunches = p->n_bunches; a.n_tiles = p->n_tiles;
+  a.dirty_mask = p->dirty_mask; a.speculator = p->speculator;
+  a.sync_idx = p->sync_idx; a.sync_val = p->sync_val; a.tail_val = p->tail_val;
+  a.bunch_row = p->bunch_row;
+  a.dbg_start = p->dbg_start; a.dbg_dirty = p->dbg_dirty; a.dbg_heads = p->dbg_heads;
+  return a;
 }
 
 // Stage 1: speculative execution.  (nnz = 0: y is zeroed here.)
@@ -1144,13 +1218,7 @@ int launch_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const 
   }
   Stage1Fn k1 = pick_stage1(p->dt, p->W, p->debug != 0);
   if (!k1) return SSS_ERR_UNSUPPORTED;
-  MatCtx a1{};
-  a1.row_ptr = row_ptr; a1.col = col; a1.val = val; a1.x = x; a1.y = y;
-  a1.m = (int32_t)p->m; a1.nnz = (int32_t)p->nnz; a1.S = p->S; a1.W = p->W; a1.n_bunches = p->n_bunches;
-  a1.n_tiles = p->n_tiles;
-  a1.dirty_mask = p->dirty_mask; a1.speculator = p->speculator; a1.sync_idx = p->sync_idx; a1.sync_val = p->sync_val;
-  a1.bunch_row = p->bunch_row;
-  a1.dbg_start = p->dbg_start; a1.dbg_dirty = p->dbg_dirty; a1.dbg_heads = p->dbg_heads;
+  const MatCtx a1 = plan_ctx(p, row_ptr, col, val, x, y);
   const int64_t blocks1 = (p->n_bunches + p->B - 1) / p->B;
   const size_t lds1 = (size_t)p->B * stage1_lds_words(p->W, p->S) * sizeof(uint32_t);
   hipLaunchKernelGGL(k1, dim3((unsigned)blocks1), dim3(p->B * kWave), lds1, stream, a1);
@@ -1163,10 +1231,7 @@ int launch_stage1(sss_plan p, const int32_t *row_ptr, const int32_t *col, const 
 int launch_stage2(sss_plan p, const int32_t *row_ptr, void *y, hipStream_t stream) {
   if (p->m == 0 || p->nnz == 0) return SSS_OK;
   const int WT = p->W * kWave;
-  MatCtx a2{};
-  a2.row_ptr = row_ptr; a2.y = y; a2.m = (int32_t)p->m; a2.nnz = (int32_t)p->nnz; a2.S = p->S; a2.W = p->W;
-  a2.n_bunches = p->n_bunches; a2.n_tiles = p->n_tiles; a2.dirty_mask = p->dirty_mask;
-  a2.speculator = p->speculator; a2.sync_idx = p->sync_idx; a2.sync_val = p->sync_val;
+  const MatCtx a2 = plan_ctx(p, row_ptr, nullptr, nullptr, nullptr, y);
   // one wavefront per 64 bunches (their carry runs), then one per thread-bunch
   // (its dirty tiles)
   const int wpb = fixup_waves_per_block(p->W, p->dt);
@@ -1215,6 +1280,14 @@ int launch_batch(sss_plan p, hipStream_t stream) {
 
 std::mutex g_cache_mu;
 std::map<std::tuple<int, void *, int64_t, int64_t, int64_t>, sss_plan> g_cache;
+
+// sss_validate_csr's result word: one per device, in the code object (no
+// allocation per call); calls are serialised by a mutex, each waits for its
+// stream before it returns
+__device__ int validate_flag;
+constexpr int kMaxDevices = 64;
+std::mutex g_validate_mu;
+int *g_validate_ptr[kMaxDevices] = {};
 
 template <int DT, int W>
 int launch_floor(sss_plan p, const MatCtx &a, void *out, int gather, hipStream_t stream) {
@@ -1267,7 +1340,7 @@ int launch_floor_w(sss_plan p, const MatCtx &a, void *out, int gather, hipStream
 // same three parts as the device kernel, on host arrays, one thread.
 template <typename YT>
 void stage2_host(sss_plan p, const int32_t *rp, YT *y, const uint32_t *dm, const int4 *spec, const int32_t *si,
-                 const double *sv) {
+                 const double *sv, const double *tv) {
   const int64_t nb = p->n_bunches;
   const int64_t WT = (int64_t)p->W * kWave, SWT = (int64_t)p->S * WT;
   // leading empty rows
@@ -1289,14 +1362,16 @@ void stage2_host(sss_plan p, const int32_t *rp, YT *y, const uint32_t *dm, const
       }
     }
   }
-  // carries: runs of bunches that begin in the same row, summed in bunch order
+  // carries: runs of bunches that begin in the same row, summed in bunch
+  // order after the tail of the bunch before the run (unless the row begins
+  // with the run)
   for (int64_t tb = 0; tb < nb;) {
     const int idx = si[tb];
     int64_t e = tb;
     double sum = 0.0;
     while (e < nb && si[e] == idx) sum += sv[e++];
     const bool fresh = (int64_t)rp[idx] == tb * SWT;
-    y[idx] = fresh ? (YT)sum : (YT)((double)y[idx] + sum);
+    y[idx] = (YT)(fresh ? sum : tv[tb - 1] + sum);
     tb = e;
   }
 }
@@ -1305,6 +1380,38 @@ void stage2_host(sss_plan p, const int32_t *rp, YT *y, const uint32_t *dm, const
 
 extern "C" {
 
+int sss_csr_spmv_plan_workspace_size(int64_t m, int64_t n, int64_t nnz, sss_dtype dt, const sss_plan_opts *opts,
+                                     size_t *bytes) {
+  if (!bytes) return SSS_ERR_INVALID_VALUE;
+  *bytes = 0;
+  if (m < 0 || n < 0 || nnz < 0 || m > SSS_MAX_INDEX || n > SSS_MAX_INDEX || nnz > SSS_MAX_INDEX)
+    return SSS_ERR_INVALID_VALUE;
+  if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
+  sss_plan_opts o{};
+  o.mode = SSS_MODE_FIXED;
+  if (opts) o = *opts;
+  if (o.mode != SSS_MODE_FIXED && o.mode != SSS_MODE_SELECTOR) return SSS_ERR_UNSUPPORTED;
+  const bool bind = o.bind_rows && m > 0 && nnz > 0, dbg = o.debug != 0;
+  size_t need = 0;
+  if (o.mode == SSS_MODE_FIXED) {
+    const int W = o.W ? o.W : default_W(dt), S = o.S ? o.S : default_S(dt);
+    if (!(W == 4 || W == 8 || W == 16)) return SSS_ERR_UNSUPPORTED;
+    if (S < 1 || S > kMaxS) return SSS_ERR_INVALID_VALUE;
+    need = aux_layout(nnz, W, S, bind, dbg).total;
+  } else {
+    // the selector's choice is not known yet: the largest of the grid's
+    // classes and the type's defaults
+    need = aux_layout(nnz, default_W(dt), default_S(dt), bind, dbg).total;
+    for (int c = 0; c < SSS_N_CLASSES; ++c) {
+      int W = 0, S = 0;
+      (void)sss_class_params(c, &W, &S);
+      need = std::max(need, aux_layout(nnz, W, S, bind, dbg).total);
+    }
+  }
+  *bytes = need;
+  return SSS_OK;
+}
+
 int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, sss_dtype dt,
                              const sss_plan_opts *opts, void *stream, sss_plan *out) {
   if (!out) return SSS_ERR_INVALID_VALUE;
@@ -1312,7 +1419,8 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
   if (m < 0 || n < 0 || nnz < 0 || m > SSS_MAX_INDEX || n > SSS_MAX_INDEX || nnz > SSS_MAX_INDEX)
     return SSS_ERR_INVALID_VALUE;
   if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
-  sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
+  sss_plan_opts o{};
+  o.mode = SSS_MODE_FIXED;
   if (opts) o = *opts;
   if (o.mode != SSS_MODE_FIXED && o.mode != SSS_MODE_SELECTOR) return SSS_ERR_UNSUPPORTED;
   int W = o.W ? o.W : default_W(dt);
@@ -1335,26 +1443,31 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
   if (!(W == 4 || W == 8 || W == 16)) return SSS_ERR_UNSUPPORTED;
   if (S < 1 || S > kMaxS || B < 1 || B > 4) return SSS_ERR_INVALID_VALUE;
   if (o.bind_rows && m > 0 && nnz > 0 && !row_ptr) return SSS_ERR_INVALID_VALUE;
+  if (!o.workspace && o.workspace_bytes) return SSS_ERR_INVALID_VALUE;
   sss_plan p = new sss_plan_s();
   p->m = m; p->n = n; p->nnz = nnz; p->dt = dt; p->W = W; p->S = S; p->B = B; p->debug = o.debug ? 1 : 0;
   p->bind_rows = (o.bind_rows && m > 0 && nnz > 0) ? 1 : 0;
+  p->bound_row_ptr = p->bind_rows ? row_ptr : nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = SSS_OK;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
-  if (rc == SSS_OK) rc = plan_alloc(p);
+  if (rc == SSS_OK) rc = plan_alloc(p, o.workspace, o.workspace_bytes, s);
   if (rc == SSS_OK && p->bind_rows) {
     // each thread-bunch's first row, once for every later call
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t SWT = (int64_t)p->S * p->W * kWave;
     const unsigned blocks = (unsigned)std::min<int64_t>((p->n_bunches + 255) / 256, 65535);
     hipLaunchKernelGGL(sss_bunch_rows, dim3(blocks), dim3(256), 0, s, row_ptr, (int32_t)m, SWT, p->n_bunches,
                        p->bunch_row);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
+  }
+  if (rc == SSS_OK) {
+    e = hipStreamSynchronize(s);
     if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
   }
   if (rc != SSS_OK) {
-    if (p->aux) (void)hipFree(p->aux);
+    if (p->owns_aux && p->aux) (void)hipFree(p->aux);
     delete p;
     return rc;
   }
@@ -1402,6 +1515,7 @@ int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *strea
   if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
   if (p->m == 0) return SSS_OK;
   if (!row_ptr || !y) return SSS_ERR_INVALID_VALUE;
+  if (p->bind_rows && row_ptr != p->bound_row_ptr) return SSS_ERR_PLAN_MISMATCH;
   return launch_stage2(p, row_ptr, y, static_cast<hipStream_t>(stream));
 }
 
@@ -1452,25 +1566,31 @@ int sss_csr_spmv_stage2_host(sss_plan p, const int32_t *row_ptr, void *y) {
   std::vector<uint32_t> dm(nb);
   std::vector<int4> spec(nb * (size_t)p->S);
   std::vector<int32_t> si(nb);
-  std::vector<double> sv(nb);
+  std::vector<double> sv(nb), tv(nb);
   SSS_HIP(hipDeviceSynchronize());
   SSS_HIP(hipMemcpy(dm.data(), p->dirty_mask, nb * sizeof(uint32_t), hipMemcpyDeviceToHost));
   SSS_HIP(hipMemcpy(spec.data(), p->speculator, spec.size() * sizeof(int4), hipMemcpyDeviceToHost));
   SSS_HIP(hipMemcpy(si.data(), p->sync_idx, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
   SSS_HIP(hipMemcpy(sv.data(), p->sync_val, nb * sizeof(double), hipMemcpyDeviceToHost));
-  if (p->dt == SSS_F64) stage2_host(p, row_ptr, static_cast<double *>(y), dm.data(), spec.data(), si.data(), sv.data());
-  else stage2_host(p, row_ptr, static_cast<float *>(y), dm.data(), spec.data(), si.data(), sv.data());
+  SSS_HIP(hipMemcpy(tv.data(), p->tail_val, nb * sizeof(double), hipMemcpyDeviceToHost));
+  if (p->dt == SSS_F64)
+    stage2_host(p, row_ptr, static_cast<double *>(y), dm.data(), spec.data(), si.data(), sv.data(), tv.data());
+  else
+    stage2_host(p, row_ptr, static_cast<float *>(y), dm.data(), spec.data(), si.data(), sv.data(), tv.data());
   return SSS_OK;
 }
 
 int sss_plan_destroy(sss_plan p) {
   if (!p) return SSS_OK;
   int rc = SSS_OK;
-  hipError_t e = hipDeviceSynchronize();
+  // hipFree waits for the device's outstanding work before it frees (so a
+  // replay of the plan's graph has ended before the graph goes); a
+  // caller-provided workspace stays with the caller
+  hipError_t e = hipSuccess;
+  if (p->owns_aux && p->aux) e = hipFree(p->aux);
   if (e == hipSuccess && p->graph_exec) e = hipGraphExecDestroy(p->graph_exec);
   if (e == hipSuccess && p->graph) e = hipGraphDestroy(p->graph);
   if (e == hipSuccess && p->capture_stream) e = hipStreamDestroy(p->capture_stream);
-  if (e == hipSuccess && p->aux) e = hipFree(p->aux);
   if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
   delete p;
   return rc;
@@ -1523,6 +1643,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   const size_t o_sp = off; off = align256(off + sizeof(int4) * (size_t)(spec_all + 1));
   const size_t o_si = off; off = align256(off + sizeof(int32_t) * (size_t)(nb_all + 1));
   const size_t o_sv = off; off = align256(off + sizeof(double) * (size_t)(nb_all + 1));
+  const size_t o_tv = off; off = align256(off + sizeof(double) * (size_t)(nb_all + 1));
   const size_t o_bi = off; off = align256(off + sizeof(int4) * (size_t)(nb_all + 1));
 
   sss_plan p = new sss_plan_s();
@@ -1534,11 +1655,13 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
     delete p;
     return SSS_ERR_HIP;
   };
+  hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) return fail(e);
   e = hipMalloc(&p->aux, off);
   if (e != hipSuccess) { p->aux = nullptr; return fail(e); }
-  e = hipMemset(p->aux, 0, off);
+  p->owns_aux = true;
+  e = hipMemsetAsync(p->aux, 0, off, s);
   if (e != hipSuccess) return fail(e);
   char *base = static_cast<char *>(p->aux);
   for (int i = 0; i < count; ++i) {
@@ -1547,10 +1670,15 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
     c.speculator = reinterpret_cast<int4 *>(base + o_sp) + sb[(size_t)i];
     c.sync_idx = reinterpret_cast<int32_t *>(base + o_si) + bb[(size_t)i];
     c.sync_val = reinterpret_cast<double *>(base + o_sv) + bb[(size_t)i];
+    c.tail_val = reinterpret_cast<double *>(base + o_tv) + bb[(size_t)i];
   }
-  if (count > 0) e = hipMemcpy(base + o_mats, ctx.data(), sizeof(MatCtx) * (size_t)count, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(base + o_bb, bb.data(), sizeof(int64_t) * ((size_t)count + 1), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(base + o_cb, cb.data(), sizeof(int64_t) * ((size_t)count + 1), hipMemcpyHostToDevice);
+  // host arrays stay alive until the stream synchronisation below
+  if (count > 0)
+    e = hipMemcpyAsync(base + o_mats, ctx.data(), sizeof(MatCtx) * (size_t)count, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + o_bb, bb.data(), sizeof(int64_t) * ((size_t)count + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + o_cb, cb.data(), sizeof(int64_t) * ((size_t)count + 1), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(e);
   BatchArgs &ba = p->bargs;
   ba.mats = reinterpret_cast<const MatCtx *>(base + o_mats);
@@ -1566,14 +1694,14 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   int4 *binfo = reinterpret_cast<int4 *>(base + o_bi);
   ba.bunch_info = binfo;
   if (nb_all > 0) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const unsigned blocks = (unsigned)std::min<int64_t>((nb_all + 255) / 256, 65535);
     hipLaunchKernelGGL(sss_batch_bunch_info, dim3(blocks), dim3(256), 0, s, ba.mats, ba.bunch_base, count, nb_all,
                        binfo);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(e);
   }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(e);
   // stage 2's persistent grid: as many workgroups as stay resident on the device
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -1675,8 +1803,16 @@ int sss_validate_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, 
   if (m < 0 || n < 0 || nnz < 0) return SSS_ERR_INVALID_VALUE;
   if (!row_ptr || (nnz > 0 && !col)) return SSS_ERR_INVALID_VALUE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int *d_bad = nullptr;
-  SSS_HIP(hipMalloc(&d_bad, sizeof(int)));
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SSS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_validate_mu);
+  if (!g_validate_ptr[dev]) {
+    void *ptr = nullptr;
+    SSS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(validate_flag)));
+    g_validate_ptr[dev] = static_cast<int *>(ptr);
+  }
+  int *d_bad = g_validate_ptr[dev];
   int rc = SSS_OK;
   hipError_t e = hipMemsetAsync(d_bad, 0, sizeof(int), s);
   if (e == hipSuccess) {
@@ -1688,7 +1824,6 @@ int sss_validate_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, 
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
-  (void)hipFree(d_bad);
   if (rc == SSS_OK && bad) rc = SSS_ERR_INVALID_CSR;
   return rc;
 }
@@ -1697,7 +1832,7 @@ int sss_plan_debug_size(sss_plan p, size_t *bytes) {
   if (!p || !bytes) return SSS_ERR_INVALID_VALUE;
   const size_t wpt = (size_t)p->W * kWave / 32;
   *bytes = 4 * sizeof(int64_t) + (size_t)p->n_tiles * (2 * sizeof(int32_t) + wpt * sizeof(uint32_t)) +
-           (size_t)p->n_tiles * 4 * sizeof(int32_t) + (size_t)p->n_bunches * (sizeof(int32_t) + sizeof(double));
+           (size_t)p->n_tiles * 4 * sizeof(int32_t) + (size_t)p->n_bunches * (sizeof(int32_t) + 2 * sizeof(double));
   return SSS_OK;
 }
 
@@ -1736,6 +1871,8 @@ int sss_plan_debug_dump(sss_plan p, void *host_buf, size_t bytes) {
   if (nb > 0) {
     SSS_HIP(hipMemcpy(cur, p->sync_idx, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
     SSS_HIP(hipMemcpy(cur + nb * sizeof(int32_t), p->sync_val, nb * sizeof(double), hipMemcpyDeviceToHost));
+    SSS_HIP(hipMemcpy(cur + nb * (sizeof(int32_t) + sizeof(double)), p->tail_val, nb * sizeof(double),
+                      hipMemcpyDeviceToHost));
   }
   return SSS_OK;
 }

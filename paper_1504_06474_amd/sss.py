@@ -49,7 +49,8 @@ class CsrDesc(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int), ("B", ctypes.c_int),
-                ("debug", ctypes.c_int), ("bind_rows", ctypes.c_int), ("batch_persistent", ctypes.c_int)]
+                ("debug", ctypes.c_int), ("bind_rows", ctypes.c_int), ("batch_persistent", ctypes.c_int),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -65,6 +66,8 @@ def lib():
         P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         L.sss_csr_spmv_plan_create.argtypes = [I64, I64, I64, P, I, ctypes.POINTER(PlanOpts), P,
                                                ctypes.POINTER(P)]
+        L.sss_csr_spmv_plan_workspace_size.argtypes = [I64, I64, I64, I, ctypes.POINTER(PlanOpts),
+                                                       ctypes.POINTER(ctypes.c_size_t)]
         L.sss_csr_spmv_execute.argtypes = [P, P, P, P, P, P, P]
         L.sss_csr_spmv.argtypes = [I64, I64, I64, P, P, P, P, P, P]
         L.sss_csr_spmv_stage1.argtypes = [P, P, P, P, P, P, P]
@@ -101,7 +104,7 @@ def lib():
         L.sss_status_string.restype = ctypes.c_char_p
         L.sss_last_hip_error.restype = ctypes.c_char_p
         L.sss_version.restype = ctypes.c_char_p
-        for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_csr_spmv_cache_clear",
+        for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_plan_workspace_size", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_csr_spmv_cache_clear",
                   "sss_plan_destroy",
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
@@ -135,18 +138,37 @@ def _stream(stream) -> Optional[int]:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def workspace_size(m: int, n: int, nnz: int, dtype=torch.float64, W: int = 0, S: int = 0,
+                   debug: bool = False, mode: int = MODE_FIXED, bind_rows: bool = False) -> int:
+    """Bytes of device workspace a plan with these options needs
+    (sss_csr_spmv_plan_workspace_size)."""
+    dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    opts = PlanOpts(mode, W, S, 0, 1 if debug else 0, 1 if bind_rows else 0)
+    b = ctypes.c_size_t()
+    _check(lib().sss_csr_spmv_plan_workspace_size(int(m), int(n), int(nnz), dt, ctypes.byref(opts),
+                                                   ctypes.byref(b)), "sss_csr_spmv_plan_workspace_size")
+    return b.value
+
+
 class Plan:
-    """A plan for y = A x on an m x n matrix with nnz nonzeros (sss_csr_spmv_plan_create)."""
+    """A plan for y = A x on an m x n matrix with nnz nonzeros (sss_csr_spmv_plan_create).
+    Its auxiliary arrays live in a uint8 tensor from PyTorch's allocator on
+    `device` (the plan's workspace), held by this object."""
 
     def __init__(self, m: int, n: int, nnz: int, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0,
                  debug: bool = False, mode: int = MODE_FIXED, row_ptr: Optional[torch.Tensor] = None,
-                 bind_rows: bool = False, stream=None):
+                 bind_rows: bool = False, stream=None, device=None):
         L = lib()
         self.m, self.n, self.nnz = int(m), int(n), int(nnz)
         self.dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
         if mode == MODE_SELECTOR and not L.sss_selector_loaded():
             load_selector()  # the network shipped with the package, once per device
-        opts = PlanOpts(mode, W, S, B, 1 if debug else 0, 1 if bind_rows else 0)
+        if device is None:
+            device = row_ptr.device if row_ptr is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = workspace_size(m, n, nnz, self.dt, W, S, debug, mode, bind_rows)
+        # 256-byte alignment: PyTorch's caching allocator hands out blocks aligned to 512 bytes
+        self._ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        opts = PlanOpts(mode, W, S, B, 1 if debug else 0, 1 if bind_rows else 0, 0, self._ws.data_ptr(), nbytes)
         h = ctypes.c_void_p()
         rc = L.sss_csr_spmv_plan_create(self.m, self.n, self.nnz, _ptr(row_ptr), self.dt, ctypes.byref(opts),
                                         _stream(stream), ctypes.byref(h))
@@ -204,10 +226,11 @@ class Plan:
         heads = buf[o:o + 4 * nt * wpt].view(np.uint32).reshape(nt, wpt); o += 4 * nt * wpt
         spec = buf[o:o + 16 * nt].view(np.int32).reshape(nt, 4)[:nd]; o += 16 * nt
         sync_idx = buf[o:o + 4 * nb].view(np.int32); o += 4 * nb
-        sync_val = buf[o:o + 8 * nb].view(np.float64)
+        sync_val = buf[o:o + 8 * nb].view(np.float64); o += 8 * nb
+        tail_val = buf[o:o + 8 * nb].view(np.float64)
         return {"n_tiles": nt, "n_bunches": nb, "dirty_count": nd, "tile_start": tile_start.copy(),
                 "tile_dirty": tile_dirty.copy(), "heads": heads.copy(), "speculator": spec.copy(),
-                "sync_idx": sync_idx.copy(), "sync_val": sync_val.copy()}
+                "sync_idx": sync_idx.copy(), "sync_val": sync_val.copy(), "tail_val": tail_val.copy()}
 
     def stage2_host(self, row_ptr: np.ndarray, y) -> None:
         """Stage 2 on a host core (sss_csr_spmv_stage2_host), for comparison

@@ -78,12 +78,37 @@ def to_dev_precision(A, x, kind):
     return rp, col, v, xx, ve, xe
 
 
-def assert_f32_path_bound(y, y_ref, scale):
-    """Reduced-precision path: float products (rounding u = 2^-24 each),
-    compensated sums (O(u^2)), one final rounding of y to float: the error
-    against the oracle on the stored values is at most 2u (|A||x|)_i."""
+U64 = 2.0 ** -53
+
+
+def f32_path_bound(scale, row_ptr):
+    """Per-row error bound of the reduced-precision path against the oracle
+    on the stored values, S = (|A||x|)_i, u = 2^-24, len = the row's length:
+
+    * products rounded once in float:            u * S
+    * y rounded once to float, |sum| <= (1+u)S:   u * (1 + u) * S
+    * compensated float pairs (TwoSum, the low part summed plainly) inside a
+      lane and through the 64-lane scan: each of at most 40 float additions
+      into a low part errs by u * (that part) <= u * u * S:   40 u^2 * S
+    * double additions of tile partials, transmitters, tails and carries: at
+      most one per tile the row touches (len / 256 + 2 at W >= 4) plus 32:
+      (len / 256 + 34) * 2^-53 * S
+    * the oracle: Dot2 (faithful, 2^-53 |y| <= 2^-53 S), and S itself summed
+      plainly in double (relative error <= len * 2^-53).
+    So |y - y_ref| <= S * (2u + 41 u^2 + (len/256 + 35) 2^-53) * (1 + len 2^-53)."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    length = (rp[1:] - rp[:-1]).astype(np.float64)
+    per_row = 2 * U32 + 41 * U32 * U32 + (length / 256.0 + 35.0) * U64
+    return scale * per_row * (1.0 + length * U64)
+
+
+def assert_f32_path_bound(y, y_ref, scale, row_ptr):
+    """Reduced-precision path: float products, compensated segment sums,
+    partials combined in double, y rounded once: the error against the
+    oracle on the stored values stays within f32_path_bound (2u (|A||x|)_i
+    up to second-order terms)."""
     y = np.asarray(y, dtype=np.float64)
-    bound = (2 * U32) * (1 + 1e-6) * scale
+    bound = f32_path_bound(scale, row_ptr)
     bad = np.abs(y - y_ref) > bound
     if bad.any():
         i = int(np.nonzero(bad)[0][0])

@@ -78,3 +78,40 @@ def test_host_side_argument_checks():
     assert L.sss_csr_spmv_stage2(None, None, None, None) == -1
     assert L.sss_csr_spmv_stage2_host(None, None, None) == -1
     assert L.sss_plan_destroy(None) == 0
+
+
+def test_workspace_size_host_side():
+    """Workspace sizes are host arithmetic (no device): FIXED mode the
+    layout of its (W, S), growing with nnz; SELECTOR mode at least every
+    grid class's; bad arguments rejected."""
+    from paper_1504_06474_amd import sss
+    L = sss.lib()
+    b = ctypes.c_size_t()
+    sizes = {}
+    for W in (4, 8, 16):
+        for S in (1, 2, 4, 8):
+            o = sss.PlanOpts(sss.MODE_FIXED, W, S, 0, 0)
+            assert L.sss_csr_spmv_plan_workspace_size(10 ** 6, 10 ** 6, 2 * 10 ** 7, 0, ctypes.byref(o),
+                                                      ctypes.byref(b)) == 0
+            sizes[W, S] = b.value
+            nb = -(-2 * 10 ** 7 // (S * W * 64))
+            # dirty mask, speculator (S per bunch), synchronizer index and value, tail
+            assert b.value >= nb * (4 + 16 * S + 4 + 8 + 8)
+    o = sss.PlanOpts(sss.MODE_SELECTOR, 0, 0, 0, 0)
+    assert L.sss_csr_spmv_plan_workspace_size(10 ** 6, 10 ** 6, 2 * 10 ** 7, 0, ctypes.byref(o), ctypes.byref(b)) == 0
+    assert b.value == max(sizes.values())
+    o = sss.PlanOpts(sss.MODE_FIXED, 8, 5, 0, 0, 1)  # bind_rows adds a first row per bunch
+    assert L.sss_csr_spmv_plan_workspace_size(10 ** 6, 10 ** 6, 2 * 10 ** 7, 0, ctypes.byref(o), ctypes.byref(b)) == 0
+    bound = b.value
+    o = sss.PlanOpts(sss.MODE_FIXED, 8, 5, 0, 0, 0)
+    assert L.sss_csr_spmv_plan_workspace_size(10 ** 6, 10 ** 6, 2 * 10 ** 7, 0, ctypes.byref(o), ctypes.byref(b)) == 0
+    assert bound > b.value
+    assert L.sss_csr_spmv_plan_workspace_size(-1, 1, 1, 0, None, ctypes.byref(b)) == -1
+    assert L.sss_csr_spmv_plan_workspace_size(1, 1, 1, 0, None, None) == -1
+    assert L.sss_csr_spmv_plan_workspace_size(1, 1, 1, 9, None, ctypes.byref(b)) == -2
+    bad = sss.PlanOpts(sss.MODE_FIXED, 5, 1, 0, 0)
+    assert L.sss_csr_spmv_plan_workspace_size(1, 1, 1, 0, ctypes.byref(bad), ctypes.byref(b)) == -2
+    # a workspace pointer with no size, or a size with no pointer
+    h = ctypes.c_void_p()
+    o = sss.PlanOpts(sss.MODE_FIXED, 8, 5, 0, 0, 0, 0, None, 64)
+    assert L.sss_csr_spmv_plan_create(10, 10, 10, None, 0, ctypes.byref(o), None, ctypes.byref(h)) == -1

@@ -120,6 +120,27 @@ def _check_dump(d, A, W, S, x):
     want = {(int(starts[t]), int(starts[t + 1]), t) for t in np.nonzero(dirty)[0]}
     assert spec == want
     assert np.array_equal(d["sync_idx"], starts[:-1][::S])
+    tails = d["tail_val"]
+    for tb, v in _expected_tails(A, x, W, S).items():
+        assert tails[tb] == v, (tb, tails[tb], v)
+
+
+def _expected_tails(A, x, W, S):
+    """Bunch tb's tail, where it has one: the products of the row holding
+    the bunch's last nonzero, from that row's head to the bunch's end, when
+    the row continues into the next bunch and is not the bunch's first row
+    (exact on integer-valued inputs)."""
+    SWT = S * W * 64
+    rp = A.row_ptr.astype(np.int64)
+    out = {}
+    for tb in range(math.ceil(A.nnz / SWT) - 1):
+        b0, e = tb * SWT, (tb + 1) * SWT
+        r0 = int(np.searchsorted(rp, b0, side="right")) - 1
+        r = int(np.searchsorted(rp, e - 1, side="right")) - 1  # the row holding nonzero e - 1
+        if rp[r + 1] > e and r != r0:
+            k = np.arange(rp[r], e)
+            out[tb] = float(np.sum(A.val[k] * x[A.col[k]]))
+    return out
 
 
 def test_debug_dump_matches_oracle_definitions(torch_cuda):
@@ -321,6 +342,83 @@ def test_bound_rows_needs_row_ptr(torch_cuda):
     from paper_1504_06474_amd import sss
     with pytest.raises(sss.SSSError):
         sss.Plan(10, 10, 10, bind_rows=True)
+
+
+def test_bound_plan_rejects_another_row_ptr(torch_cuda):
+    """A plan bound to one row_ptr array returns PLAN_MISMATCH for another
+    (execute, stage 1 and stage 2 alike); an unbound plan takes any."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1(int_valued=True)
+    rp, col, v, xx = to_dev(A, x)
+    other = rp.clone()
+    plan = sss.Plan(A.m, A.n, A.nnz, bind_rows=True, row_ptr=rp)
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    for call in (lambda: plan.execute(other, col, v, xx, y), lambda: plan.stage1(other, col, v, xx, y),
+                 lambda: plan.stage2(other, y)):
+        with pytest.raises(sss.SSSError) as e:
+            call()
+        assert e.value.status == -3
+    plan.execute(rp, col, v, xx, y)
+    free = sss.Plan(A.m, A.n, A.nnz)
+    y2 = free.execute(other, col, v, xx)
+    torch.cuda.synchronize()
+    want = oracle.spmv(A.row_ptr, A.col, A.val, x)
+    assert_exact(y.cpu().numpy(), want)
+    assert_exact(y2.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
+def test_bound_plan_row_ptr_rewritten_in_place(torch_cuda, WS):
+    """The same row_ptr array rewritten in place with another structure of
+    the same m and nnz: stage 1 finds its stored first rows no longer hold
+    and searches, so y is still exact (and matches a fresh plan's)."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1(int_valued=True)
+    lens = np.diff(A.row_ptr.astype(np.int64))
+    lens2 = csrgen.rng_for(11).permutation(lens)
+    rp2 = np.zeros(A.m + 1, dtype=np.int64)
+    np.cumsum(lens2, out=rp2[1:])
+    A2 = csrgen.CSR(A.m, A.n, rp2.astype(np.int32), A.col, A.val, "config1_rows_permuted")
+    rp, col, v, xx = to_dev(A, x)
+    plan = sss.Plan(A.m, A.n, A.nnz, W=WS[0], S=WS[1], bind_rows=True, row_ptr=rp)
+    y1 = plan.execute(rp, col, v, xx).cpu().numpy()
+    rp.copy_(torch.from_numpy(A2.row_ptr).to("cuda"))
+    y2 = plan.execute(rp, col, v, xx).cpu().numpy()
+    assert_exact(y1, oracle.spmv(A.row_ptr, A.col, A.val, x))
+    assert_exact(y2, oracle.spmv(A2.row_ptr, A2.col, A2.val, x))
+
+
+def test_plan_workspace(torch_cuda):
+    """A plan in a caller's workspace (as the binding makes them, from
+    PyTorch's allocator) and a plan with its own allocation give bitwise the
+    same y; a workspace that is too small or misaligned is rejected."""
+    import ctypes
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1()
+    rp, col, v, xx = to_dev(A, x)
+    L = sss.lib()
+    need = sss.workspace_size(A.m, A.n, A.nnz, W=8, S=5)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    for ptr, size in ((ws.data_ptr(), need - 1), (ws.data_ptr() + 16, need)):
+        o = sss.PlanOpts(sss.MODE_FIXED, 8, 5, 0, 0, 0, 0, ptr, size)
+        assert L.sss_csr_spmv_plan_create(A.m, A.n, A.nnz, None, 0, ctypes.byref(o), None, ctypes.byref(h)) == -1
+        assert h.value is None
+    o = sss.PlanOpts(sss.MODE_FIXED, 8, 5, 0, 0, 0, 0, None, 0)
+    assert L.sss_csr_spmv_plan_create(A.m, A.n, A.nnz, None, 0, ctypes.byref(o), None, ctypes.byref(h)) == 0
+    y_own = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    assert L.sss_csr_spmv_execute(h, rp.data_ptr(), col.data_ptr(), v.data_ptr(), xx.data_ptr(), y_own.data_ptr(),
+                                  None) == 0
+    torch.cuda.synchronize()
+    assert L.sss_plan_destroy(h) == 0
+    y_ws = sss.Plan(A.m, A.n, A.nnz, W=8, S=5).execute(rp, col, v, xx)
+    torch.cuda.synchronize()
+    assert np.array_equal(y_own.cpu().numpy().view(np.int64), y_ws.cpu().numpy().view(np.int64))
+    assert_f64_parity(y_ws.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x),
+                      oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
 
 
 @pytest.mark.parametrize("bind", [False, True])
