@@ -53,7 +53,8 @@ typedef enum {
   SSS_ERR_UNSUPPORTED = -2,    /* dtype or parameter combination not built */
   SSS_ERR_PLAN_MISMATCH = -3,  /* plan used on another device, or a bind_rows plan with another row_ptr */
   SSS_ERR_HIP = -4,            /* a HIP runtime call failed */
-  SSS_ERR_INVALID_CSR = -5     /* sss_validate_csr found a malformed matrix */
+  SSS_ERR_INVALID_CSR = -5,    /* sss_validate_csr found a malformed matrix */
+  SSS_ERR_TOO_LARGE = -6       /* sss_csr_spmv_noalloc: the matrix needs more than its static scratch */
 } sss_status;
 
 /* Value type.  SSS_F64: val, x, y are double.  SSS_F32: val, x, y are float.
@@ -187,6 +188,24 @@ int sss_csr_spmv_stage2_host(sss_plan p, const int32_t *row_ptr, void *y);
 int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                  const int32_t *col, const double *val, const double *x, double *y,
                  void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as sss_csr_spmv (double precision, the default parameters, the same
+ * kernels, so the same y bit for bit) with the plan's auxiliary arrays in a
+ * static device array of 16 MiB that the library holds on each device until
+ * the process ends, instead of a cached plan.  Allocates nothing and never
+ * synchronises; on a device's first call it looks up that array's address
+ * (hipGetSymbolAddress).  Limit: the arrays take about 104 bytes per 2,560
+ * nonzeros, so nnz up to about 412 million (beyond: SSS_ERR_TOO_LARGE, before
+ * any device work).  Every call on a device shares that one array: calls that
+ * overlap on one device (two streams, or two host threads) race and give
+ * wrong results; order them on one stream.  Each call leaves the array
+ * holding its own intermediate state, which the next call overwrites (nothing
+ * needs clearing).  Other arguments and errors as for sss_csr_spmv. */
+int sss_csr_spmv_noalloc(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
+                         const int32_t *col, const double *val, const double *x, double *y,
+                         void *stream);
 
 /* Free every plan sss_csr_spmv has cached, on every device and stream (a
  * process that sees many sizes can bound its memory this way).  Waits for

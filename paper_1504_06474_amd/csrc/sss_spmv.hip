@@ -1289,6 +1289,17 @@ constexpr int kMaxDevices = 64;
 std::mutex g_validate_mu;
 int *g_validate_ptr[kMaxDevices] = {};
 
+// sss_csr_spmv_noalloc's plan arrays (dirty masks, speculator, synchronizer,
+// tails of a default double-precision plan): a static array in the code
+// object, one per device, held until the process ends.  Host code never uses
+// its name as an address: the device address comes from hipGetSymbolAddress,
+// once per device.  Every call on a device shares it; stage 1 writes every
+// entry stage 2 reads, so nothing needs clearing between calls.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
 template <int DT, int W>
 int launch_floor(sss_plan p, const MatCtx &a, void *out, int gather, hipStream_t stream) {
   using y_t = typename VT<DT>::y_t;
@@ -1539,6 +1550,34 @@ int sss_csr_spmv(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, cons
     }
   }
   return launch(p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sss_csr_spmv_noalloc(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+                         const double *val, const double *x, double *y, void *stream) {
+  if (m < 0 || n < 0 || nnz < 0 || m > SSS_MAX_INDEX || n > SSS_MAX_INDEX || nnz > SSS_MAX_INDEX)
+    return SSS_ERR_INVALID_VALUE;
+  if (m == 0) return SSS_OK;
+  const AuxLayout L = aux_layout(nnz, default_W(SSS_F64), default_S(SSS_F64), false, false);
+  if (L.total > kScratchBytes) return SSS_ERR_TOO_LARGE;
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SSS_ERR_UNSUPPORTED;
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *ptr = nullptr;
+      SSS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+      g_scratch_ptr[dev] = ptr;
+    }
+    base = g_scratch_ptr[dev];
+  }
+  sss_plan_s p;
+  p.device = dev;
+  p.m = m; p.n = n; p.nnz = nnz; p.dt = SSS_F64;
+  p.W = default_W(SSS_F64); p.S = default_S(SSS_F64); p.B = kDefaultB;
+  plan_bind_aux(&p, L, base);
+  return launch(&p, row_ptr, col, val, x, y, static_cast<hipStream_t>(stream));
 }
 
 int sss_csr_spmv_cache_clear(void) {
@@ -1885,6 +1924,7 @@ const char *sss_status_string(int status) {
     case SSS_ERR_PLAN_MISMATCH: return "plan does not match the call";
     case SSS_ERR_HIP: return "HIP runtime error";
     case SSS_ERR_INVALID_CSR: return "malformed CSR matrix";
+    case SSS_ERR_TOO_LARGE: return "matrix too large for the static scratch of sss_csr_spmv_noalloc";
     default: return "unknown status";
   }
 }

@@ -25,7 +25,7 @@ _XTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
 _VALTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
 
 STATUS = {0: "ok", -1: "invalid value", -2: "unsupported", -3: "plan mismatch", -4: "HIP error",
-          -5: "invalid CSR"}
+          -5: "invalid CSR", -6: "too large for the static scratch"}
 
 
 class SSSLibraryMissing(RuntimeError):
@@ -70,6 +70,7 @@ def lib():
                                                        ctypes.POINTER(ctypes.c_size_t)]
         L.sss_csr_spmv_execute.argtypes = [P, P, P, P, P, P, P]
         L.sss_csr_spmv.argtypes = [I64, I64, I64, P, P, P, P, P, P]
+        L.sss_csr_spmv_noalloc.argtypes = [I64, I64, I64, P, P, P, P, P, P]
         L.sss_csr_spmv_stage1.argtypes = [P, P, P, P, P, P, P]
         L.sss_csr_spmv_stage2.argtypes = [P, P, P, P]
         L.sss_plan_destroy.argtypes = [P]
@@ -104,7 +105,8 @@ def lib():
         L.sss_status_string.restype = ctypes.c_char_p
         L.sss_last_hip_error.restype = ctypes.c_char_p
         L.sss_version.restype = ctypes.c_char_p
-        for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_plan_workspace_size", "sss_csr_spmv_execute", "sss_csr_spmv", "sss_csr_spmv_cache_clear",
+        for f in ("sss_csr_spmv_plan_create", "sss_csr_spmv_plan_workspace_size", "sss_csr_spmv_execute", "sss_csr_spmv",
+                  "sss_csr_spmv_noalloc", "sss_csr_spmv_cache_clear",
                   "sss_plan_destroy",
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
@@ -467,6 +469,22 @@ def csr_spmv(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: tor
             raise TypeError("sss_csr_spmv is the double-precision form")
     rc = lib().sss_csr_spmv(m, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y), _stream(stream))
     _check(rc, "sss_csr_spmv")
+    return y
+
+
+def csr_spmv_noalloc(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,
+                     y: torch.Tensor, n: Optional[int] = None, stream=None) -> torch.Tensor:
+    """The allocation-free one-call form, sss_csr_spmv_noalloc: y must be given
+    (the library allocates nothing; its static scratch serves one call at a
+    time per device)."""
+    m = row_ptr.numel() - 1
+    n = x.numel() if n is None else int(n)
+    for t in (val, x, y):
+        if t.dtype != torch.float64:
+            raise TypeError("sss_csr_spmv_noalloc is the double-precision form")
+    rc = lib().sss_csr_spmv_noalloc(m, n, val.numel(), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
+                                    _stream(stream))
+    _check(rc, "sss_csr_spmv_noalloc")
     return y
 
 
