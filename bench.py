@@ -141,6 +141,42 @@ def cpu_baseline(A, x, seconds: float) -> dict:
             "cpu_model": _cpu_model(), "comparators": comparators}
 
 
+class PlanSet:
+    """The plans for a set of rotated copies: with bound rows one plan per
+    copy (a bound plan serves only the row_ptr array it was made for), else
+    one plan shared by all.  Calls go to the plan of the copy's row_ptr."""
+
+    def __init__(self, sss, copies, m, n, nnz, bind_rows: bool, **kw):
+        if bind_rows:
+            self.plans = {c[0].data_ptr(): sss.Plan(m, n, nnz, bind_rows=True, row_ptr=c[0], **kw) for c in copies}
+        else:
+            shared = sss.Plan(m, n, nnz, row_ptr=copies[0][0], **kw)
+            self.plans = {c[0].data_ptr(): shared for c in copies}
+        self.first = next(iter(self.plans.values()))
+
+    def for_rp(self, rp):
+        return self.plans[rp.data_ptr()]
+
+    def execute(self, rp, col, v, xx, y):
+        return self.for_rp(rp).execute(rp, col, v, xx, y)
+
+    def stage1(self, rp, col, v, xx, y):
+        self.for_rp(rp).stage1(rp, col, v, xx, y)
+
+    def stage2(self, rp, y):
+        self.for_rp(rp).stage2(rp, y)
+
+    def floor_probe(self, col, v, xx, out, gather):
+        return self.first.floor_probe(col, v, xx, out, gather)  # the probe reads no row structure
+
+    def info(self):
+        return self.first.info()
+
+    def close(self):
+        for p in {id(p): p for p in self.plans.values()}.values():
+            p.close()
+
+
 def time_steps(torch, plan, copies, steps: int, warmup: int) -> float:
     """Average ms per y = A x over `steps` launches, rotating the copies."""
     for k in range(warmup):
@@ -243,14 +279,15 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                 v = torch.from_numpy(np.ascontiguousarray(vs)).cuda()
             xx = torch.from_numpy(np.ascontiguousarray(xs)).cuda()
             ydt = torch.float64 if kind == "f64" else torch.float32
-            plan = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind], bind_rows=True, row_ptr=rp)
-            info = plan.info()
-            rec = out.setdefault(kind, {"W": info["W"], "S": info["S"]})
+            copies = [(rp, col, v, xx, torch.empty(A.m, dtype=ydt, device="cuda"))]
             if values == "uniform":
-                copies = [(rp, col, v, xx, torch.empty(A.m, dtype=ydt, device="cuda"))]
                 for _ in range(2):
                     copies.append((rp.clone(), col.clone(), v.clone(), xx.clone(),
                                    torch.empty(A.m, dtype=ydt, device="cuda")))
+            plan = PlanSet(sss, copies, A.m, A.n, A.nnz, True, dtype=tdt[kind])
+            info = plan.info()
+            rec = out.setdefault(kind, {"W": info["W"], "S": info["S"]})
+            if values == "uniform":
                 ms = time_steps(torch, plan, copies, steps, warmup)
                 vb, xb = sizes[kind]
                 rec.update({"us": round(ms * 1e3, 2), "GFLOPs": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
@@ -278,18 +315,17 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                     log(f"[bench] precision f64 row-wise comparators: {rec['vs_rowwise']}")
                 # the learned selector's plan for the same matrix and value type
                 if sss.load_selector():
-                    sel = sss.Plan(A.m, A.n, A.nnz, dtype=tdt[kind], mode=sss.MODE_SELECTOR, row_ptr=rp,
-                                   bind_rows=True)
+                    sel = PlanSet(sss, copies, A.m, A.n, A.nnz, True, dtype=tdt[kind], mode=sss.MODE_SELECTOR)
                     ms_sel = time_steps(torch, sel, copies, steps, warmup)
                     rec["selected"] = {"W": sel.info()["W"], "S": sel.info()["S"], "us": round(ms_sel * 1e3, 2)}
                     sel.close()
                     # the timed output must stay the default plan's
                     plan.execute(*copies[0])
                 y = copies[0][4]
-                del copies
             else:
-                y = torch.empty(A.m, dtype=ydt, device="cuda")
-                plan.execute(rp, col, v, xx, y)
+                y = copies[0][4]
+                plan.execute(*copies[0])
+            del copies
             torch.cuda.synchronize()
             yh = y.double().cpu().numpy()
             rec.setdefault("err_vs_f64", {})[values] = error_stats(yh, ref64, sc64)
@@ -329,7 +365,7 @@ def reduced_on_benchmark_matrix(torch, sss, A, x, ms_f64: float, steps: int, war
         for _ in range(2):
             copies.append((rp.clone(), col.clone(), v.clone(), xx.clone(),
                            torch.empty(A.m, dtype=torch.float32, device="cuda")))
-        plan = sss.Plan(A.m, A.n, A.nnz, dtype=vdt, bind_rows=True, row_ptr=rp)
+        plan = PlanSet(sss, copies, A.m, A.n, A.nnz, True, dtype=vdt)
         ms = time_steps(torch, plan, copies, steps, warmup)
         info = plan.info()
         vb = 4 if kind == "f32" else 2
@@ -352,13 +388,14 @@ def host_stage2_block(torch, sss, plan, copies, A, x, reps: int = 20) -> dict:
     parts = np.zeros((reps, 3))
     for k in range(reps + 2):
         rp, col, v, xx, y = copies[k % len(copies)]
+        p = plan.for_rp(rp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan.stage1(rp, col, v, xx, y)
+        p.stage1(rp, col, v, xx, y)
         y_pin.copy_(y, non_blocking=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        plan.stage2_host(A.row_ptr, y_pin)
+        p.stage2_host(A.row_ptr, y_pin)
         t2 = time.perf_counter()
         y.copy_(y_pin, non_blocking=True)
         torch.cuda.synchronize()
@@ -659,8 +696,7 @@ def main():
     # plan / analyse (outside the timed region): with bind_rows the tile
     # boundary search runs once here instead of in every call
     bind = not args.no_bind_rows
-    plan = sss.Plan(m, n, nnz, dtype=torch.float64, W=args.W, S=args.S, B=args.B, bind_rows=bind,
-                    row_ptr=copies[0][0])
+    plan = PlanSet(sss, copies, m, n, nnz, bind, dtype=torch.float64, W=args.W, S=args.S, B=args.B)
     info = plan.info()
     log(f"[bench] plan {info}")
     torch.cuda.synchronize()
@@ -746,8 +782,7 @@ def main():
     # the other plan variant (first rows searched in every call, or bound)
     ms_other = s1_other = float("nan")
     if not args.skip_extras:
-        other = sss.Plan(m, n, nnz, dtype=torch.float64, W=args.W, S=args.S, B=args.B, bind_rows=not bind,
-                         row_ptr=copies[0][0])
+        other = PlanSet(sss, copies, m, n, nnz, not bind, dtype=torch.float64, W=args.W, S=args.S, B=args.B)
         ms_other = time_steps(torch, other, copies, args.steps, args.warmup)
         torch.cuda.synchronize()
         for k in range(args.steps):

@@ -361,6 +361,28 @@ int sss_floor_probe(sss_plan p, const int32_t *col, const void *val, const void 
  * batch_persistent plan.  Asynchronous on `stream`. */
 int sss_batch_floor_probe(sss_plan p, void *out, int gather, void *stream);
 
+/* Measurement aid, not part of the method: how fast the device serves random
+ * gathers x[col[k]] at all, with none of stage 1's choices (Section 4.4 judges
+ * the method by bandwidth utilisation; this is the ceiling the gathers put on
+ * it).  A grid-stride loop gives every lane one nonzero per iteration
+ * (k = thread + i * threads: col and val read coalesced) and keeps `unroll`
+ * (1, 2, 4, 8 or 16) gathers in flight before using any; with_val also
+ * streams val and multiplies (all the reads of a CSR SpMV, without its row
+ * structure).  mode 0: plain vector loads; 1: non-temporal loads; 2: direct-
+ * to-LDS loads (a gather in flight holds no VGPR); 3: buffer loads at device
+ * scope (not kept in the CU's L1); plus 4: every wavefront sweeps its own
+ * contiguous chunk of the nonzeros (64 at a time) instead of the whole grid
+ * sweeping them as one front.  waves_per_simd (1, 2, 4 or 8) caps the
+ * occupancy by reserving LDS; the registers may cap it lower, and
+ * *resident_per_cu receives the workgroups (of 4 wavefronts) per CU actually
+ * launched.  dt is SSS_F64 (x, val double) or SSS_F32 (float); every column
+ * must be in [0, n).  out (device, the x type) receives one sum per thread:
+ * *threads entries, at most out_len.  Asynchronous on `stream`. */
+int sss_gather_probe(const int32_t *col, const void *val, const void *x, int64_t nnz, int64_t n, sss_dtype dt,
+                     int mode, int unroll, int waves_per_simd, int with_val, void *out, int64_t out_len,
+                     int64_t *threads, int *resident_per_cu, void *stream);
+const char *sss_probe_last_hip_error(void);
+
 /* GRID-mode plan (the selector's fallback, and the yardstick of its regret):
  * runs sss_csr_spmv_autotune on the caller's matrix and returns in *out a
  * plan with the fastest class's (W, S), the default B and the rows bound

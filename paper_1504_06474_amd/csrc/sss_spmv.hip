@@ -12,8 +12,10 @@
 //     for each non-empty row), finds every tile's start row (the rightmost
 //     match of each tile boundary, counted by ballots) and detects the dirty
 //     tiles (an empty row among rows start..stop-1 of the tile);
-//   * per tile: coalesced vector loads of col/val (lane j owns entries
-//     [jW, jW+W)), gathers of x, an exclusive scan of head counts giving each
+//   * per tile: coalesced vector loads of col/val in a grouped order (lane
+//     j loads G consecutive entries of each row of 64*G; 16 bytes of values
+//     per load), gathers of x in the same order, the products moved through
+//     LDS to lane j's entries [jW, jW+W), an exclusive scan of head counts giving each
 //     partial sum its compact rank q, one pass over the lane's products that
 //     stores every segment closed inside the lane, a 64-lane segmented scan
 //     of the lanes' open segments (DPP) that completes the segments crossing
@@ -94,7 +96,7 @@ typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 #endif
 
 // streaming loads of the matrix arrays (plain loads stream faster than
-// non-temporal ones on gfx950 for this lane-contiguous pattern)
+// non-temporal ones on gfx950 for this pattern)
 template <typename T>
 __device__ __forceinline__ T stream_load(const T *p) {
   if constexpr (SSS_NT_LOADS) return __builtin_nontemporal_load(p);
@@ -167,69 +169,12 @@ template <int DT> using Acc = typename AccSel<DT>::type;
 
 // ---------------------------------------------------------------- loads
 
-// Lane-contiguous loads of W entries starting at k0 (k0 a multiple of W, the
-// arrays 16-byte aligned).
-template <int W>
-__device__ __forceinline__ void load_cols(const int32_t *__restrict__ col, int k0, int (&c)[W]) {
-  static_assert(W % 4 == 0, "W must be a multiple of 4");
-  const v4i *p = reinterpret_cast<const v4i *>(col + k0);
-#pragma unroll
-  for (int i = 0; i < W / 4; ++i) {
-    v4i v = stream_load(p + i);
-    c[4 * i + 0] = v.x; c[4 * i + 1] = v.y; c[4 * i + 2] = v.z; c[4 * i + 3] = v.w;
-  }
-}
-
-template <int W>
-__device__ __forceinline__ void load_vals(const double *__restrict__ val, int k0, double (&a)[W]) {
-  const v2d *p = reinterpret_cast<const v2d *>(val + k0);
-#pragma unroll
-  for (int i = 0; i < W / 2; ++i) {
-    v2d v = stream_load(p + i);
-    a[2 * i] = v.x; a[2 * i + 1] = v.y;
-  }
-}
-
-template <int W>
-__device__ __forceinline__ void load_vals(const float *__restrict__ val, int k0, float (&a)[W]) {
-  const v4f *p = reinterpret_cast<const v4f *>(val + k0);
-#pragma unroll
-  for (int i = 0; i < W / 4; ++i) {
-    v4f v = stream_load(p + i);
-    a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
-  }
-}
-
-template <int W>
-__device__ __forceinline__ void load_vals(const uint16_t *__restrict__ val, int k0, float (&a)[W]) {
-  if constexpr (W % 8 == 0) {
-    const v4u *p = reinterpret_cast<const v4u *>(val + k0);
-#pragma unroll
-    for (int i = 0; i < W / 8; ++i) {
-      v4u v = stream_load(p + i);
-      unsigned w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        a[8 * i + 2 * j] = bf16_to_f32(w[j] & 0xffffu);
-        a[8 * i + 2 * j + 1] = bf16_to_f32(w[j] >> 16);
-      }
-    }
-  } else {
-    const v2u *p = reinterpret_cast<const v2u *>(val + k0);
-#pragma unroll
-    for (int i = 0; i < W / 4; ++i) {
-      v2u v = stream_load(p + i);
-      a[4 * i] = bf16_to_f32(v.x & 0xffffu);
-      a[4 * i + 1] = bf16_to_f32(v.x >> 16);
-      a[4 * i + 2] = bf16_to_f32(v.y & 0xffffu);
-      a[4 * i + 3] = bf16_to_f32(v.y >> 16);
-    }
-  }
-}
-
 __device__ __forceinline__ double scalar_val(const double *v, int k) { return v[k]; }
 __device__ __forceinline__ float scalar_val(const float *v, int k) { return v[k]; }
 __device__ __forceinline__ float scalar_val(const uint16_t *v, int k) { return bf16_to_f32(v[k]); }
+
+// Integer minimum (HIP's min for 64-bit integers goes through double).
+__device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 // ---------------------------------------------------------------- search
 
@@ -361,22 +306,137 @@ struct MatCtx {
 // (padded to 2 words), then W*T double slots for one tile's compact partials.
 __host__ __device__ constexpr int stage1_lds_words(int W, int S) { return S * (W * kWave / 32) + 2 + 2 * W * kWave; }
 
-// col/val of one tile, lane-contiguous (lane j: entries [jW, jW+W)); entries
-// past nnz read as column 0 with value 0.
-template <int W, typename val_t, typename prod_t>
-__device__ __forceinline__ void load_tile(const int32_t *__restrict__ col, const val_t *__restrict__ val, int b,
-                                          int nnz, int lane, int (&c)[W], prod_t (&av)[W]) {
-  const int k0 = b + lane * W;
-  if (b + W * kWave <= nnz) {
-    load_cols<W>(col, k0, c);
-    load_vals<W>(val, k0, av);
+// Grouped order of a tile's entries: the tile is W/G rows of 64*G entries,
+// and lane j holds G consecutive entries of every row, so entry (r, g) of
+// lane j (array index r*G + g) is tile offset r*64*G + j*G + g.  G entries
+// of the value type make 16 bytes (G = W when that is fewer), so every load
+// instruction of the wavefront reads one contiguous 1-KiB stretch of val,
+// and the x gathers of one instruction fall on 64*G consecutive nonzeros.
+template <int DT> constexpr int group_of() { return DT == SSS_F64 ? 2 : (DT == SSS_F32 ? 4 : 8); }
+template <int DT, int W> constexpr int group_w() { return group_of<DT>() < W ? group_of<DT>() : W; }
+
+template <int G>
+__device__ __forceinline__ void load_cols_g(const int32_t *__restrict__ p, int *c) {
+  if constexpr (G == 2) {
+    const v2u v = stream_load(reinterpret_cast<const v2u *>(p));
+    c[0] = (int)v.x; c[1] = (int)v.y;
   } else {
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const int k = k0 + i;
-      const bool in = k < nnz;
-      c[i] = in ? col[k] : 0;
-      av[i] = in ? (prod_t)scalar_val(val, k) : (prod_t)0;
+    for (int i = 0; i < G / 4; ++i) {
+      const v4i v = stream_load(reinterpret_cast<const v4i *>(p) + i);
+      c[4 * i] = v.x; c[4 * i + 1] = v.y; c[4 * i + 2] = v.z; c[4 * i + 3] = v.w;
+    }
+  }
+}
+
+template <int G>
+__device__ __forceinline__ void load_vals_g(const double *__restrict__ p, double *a) {
+  static_assert(G % 2 == 0, "double groups are pairs");
+#pragma unroll
+  for (int i = 0; i < G / 2; ++i) {
+    const v2d v = stream_load(reinterpret_cast<const v2d *>(p) + i);
+    a[2 * i] = v.x; a[2 * i + 1] = v.y;
+  }
+}
+template <int G>
+__device__ __forceinline__ void load_vals_g(const float *__restrict__ p, float *a) {
+  static_assert(G % 4 == 0, "float groups are quadruples");
+#pragma unroll
+  for (int i = 0; i < G / 4; ++i) {
+    const v4f v = stream_load(reinterpret_cast<const v4f *>(p) + i);
+    a[4 * i] = v.x; a[4 * i + 1] = v.y; a[4 * i + 2] = v.z; a[4 * i + 3] = v.w;
+  }
+}
+template <int G>
+__device__ __forceinline__ void load_vals_g(const uint16_t *__restrict__ p, float *a) {
+  if constexpr (G == 8) {
+    const v4u v = stream_load(reinterpret_cast<const v4u *>(p));
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { a[2 * j] = bf16_to_f32(w[j] & 0xffffu); a[2 * j + 1] = bf16_to_f32(w[j] >> 16); }
+  } else {
+    static_assert(G == 4, "bfloat16 groups are 4 or 8");
+    const v2u v = stream_load(reinterpret_cast<const v2u *>(p));
+    a[0] = bf16_to_f32(v.x & 0xffffu); a[1] = bf16_to_f32(v.x >> 16);
+    a[2] = bf16_to_f32(v.y & 0xffffu); a[3] = bf16_to_f32(v.y >> 16);
+  }
+}
+
+// col/val of one tile in the grouped order; entries past nnz read as column 0
+// with value 0.
+template <int DT, int W, typename val_t, typename prod_t>
+__device__ __forceinline__ void load_tile_g(const int32_t *__restrict__ col, const val_t *__restrict__ val, int b,
+                                            int nnz, int lane, int (&c)[W], prod_t (&av)[W]) {
+  constexpr int G = group_w<DT, W>();
+  constexpr int R = W / G;
+  if (b + W * kWave <= nnz) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k0 = b + r * kWave * G + lane * G;
+      load_cols_g<G>(col + k0, &c[r * G]);
+      load_vals_g<G>(val + k0, &av[r * G]);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int k = b + r * kWave * G + lane * G + g;
+        const bool in = k < nnz;
+        c[r * G + g] = in ? col[k] : 0;
+        av[r * G + g] = in ? (prod_t)scalar_val(val, k) : (prod_t)0;
+      }
+  }
+}
+
+// The products leave the grouped order through LDS: each lane writes its G
+// products of every row as 16-byte chunks, then reads back the W products
+// of tile offsets lane*W .. lane*W+W-1 (the order the segmented sum walks).
+// 16-byte chunk c is stored at chunk c ^ ((c >> 4) & (K - 1)), K = the chunks
+// one lane reads: the 16 lanes of a read then touch 16 different chunk
+// columns of a 256-byte LDS row, as do the lanes of a write.
+template <typename P, int W>
+__device__ __forceinline__ int tr_chunk(int c) {
+  constexpr int K = (W * (int)sizeof(P)) / 16 > 0 ? (W * (int)sizeof(P)) / 16 : 1;
+  return c ^ ((c >> 4) & (K - 1));
+}
+
+template <int DT, int W, typename P>
+__device__ __forceinline__ void products_out(const P (&av)[W], const P (&xv)[W], P *buf, int lane, P (&pr)[W]) {
+  constexpr int G = group_w<DT, W>();
+  constexpr int R = W / G;
+  constexpr int CH = 16 / (int)sizeof(P);  // products per 16-byte chunk
+  static_assert(W % CH == 0, "a lane's products fill whole chunks");
+  if constexpr (G == W) {
+    // one row per tile: the grouped order is the lane order already
+#pragma unroll
+    for (int i = 0; i < W; ++i) pr[i] = av[i] * xv[i];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < G / CH; ++t) {
+        const int c = (r * kWave * G + lane * G) / CH + t;
+        P *dst = buf + tr_chunk<P, W>(c) * CH;
+#pragma unroll
+        for (int e = 0; e < CH; ++e) dst[e] = av[r * G + t * CH + e] * xv[r * G + t * CH + e];
+      }
+  }
+}
+
+template <int DT, int W, typename P>
+__device__ __forceinline__ void products_in(const P *buf, int lane, P (&pr)[W]) {
+  constexpr int CH = 16 / (int)sizeof(P);
+  if constexpr (group_w<DT, W>() != W) {
+    // one wavefront owns buf and its LDS operations run in order; the
+    // fence keeps the compiler from moving a read above another lane's write
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < W / CH; ++k) {
+      const P *src = buf + tr_chunk<P, W>((lane * W) / CH + k) * CH;
+#pragma unroll
+      for (int e = 0; e < CH; ++e) pr[k * CH + e] = src[e];
     }
   }
 }
@@ -404,12 +464,12 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
 
   const int64_t SWT = (int64_t)S * WT;
   const int b0 = (int)(tb * SWT);  // < nnz
-  const int bS = (int)min<int64_t>(tb * SWT + SWT, nnz);
+  const int bS = (int)imin64(tb * SWT + SWT, nnz);
 
   // ---- tile 0's col/val do not depend on the row structure: issue first
   int cc[W];
   prod_t av[W];
-  load_tile<W>(col, val, b0, nnz, lane, cc, av);
+  load_tile_g<DT, W>(col, val, b0, nnz, lane, cc, av);
 
   // ---- tile boundary search (rightmost match) for the bunch's first row,
   // unless the plan found it once for all calls; such a row is checked in the
@@ -428,7 +488,7 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
   if (lane == 0) *dflag = 0u;
   __builtin_amdgcn_wave_barrier();
 
-  const int my_b = (int)min<int64_t>(tb * SWT + (int64_t)min(lane, S) * WT, nnz);
+  const int my_b = (int)imin64(tb * SWT + (int64_t)min(lane, S) * WT, nnz);
   int my_count = 0;  // lane t <= S: rows r >= r0 with rp[r] <= b_t
   int my_rp = 0;     // lane t <= S: rp of the last such row (the tile's start row)
   for (int rbase = r0;; rbase += kWave) {
@@ -478,7 +538,7 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     const int64_t b64 = tb * SWT + (int64_t)t * WT;
     if (b64 >= nnz) break;
     const int b = (int)b64;
-    const int e = (int)min<int64_t>(b64 + WT, nnz);
+    const int e = (int)imin64(b64 + WT, nnz);
     const int start = __shfl(my_start, t, kWave);
     const int stop = __shfl(my_start, t + 1, kWave);
     const int rp_stop = __shfl(my_rp, t + 1, kWave);
@@ -490,7 +550,7 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     // ---- prefetch the next tile's col/val; products of this tile
     int cn[W];
     prod_t an[W];
-    if (has_next) load_tile<W>(col, val, b + WT, nnz, lane, cn, an);
+    if (has_next) load_tile_g<DT, W>(col, val, b + WT, nnz, lane, cn, an);
     // ---- this lane's W descriptor bits; the tile's first bit is forced
     uint32_t hb = (mask[t * WPT + ((lane * W) >> 5)] >> ((lane * W) & 31)) & LOW;
     const bool bit0 = __builtin_amdgcn_readlane((int)hb, 0) & 1;
@@ -520,6 +580,16 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     // every later head closes a segment that lies wholly in this lane, whose
     // partial goes to its LDS slot at once; `run` = the entries after the
     // last head (a segment still open at the lane's end).
+    // ---- the lane's W products, from the grouped order of the loads to the
+    // order of its entries lane*W .. lane*W+W-1, through `part` (no partial
+    // is staged there yet); the next tile's x gathers go out in between
+    prod_t pr[W];
+    products_out<DT, W>(av, xv, reinterpret_cast<prod_t *>(part), lane, pr);
+    if (has_next) {
+#pragma unroll
+      for (int i = 0; i < W; ++i) { xv[i] = (prod_t)x[cn[i]]; av[i] = an[i]; }
+    }
+    products_in<DT, W>(reinterpret_cast<const prod_t *>(part), lane, pr);
     Acc<DT> pre, run;
     pre.zero();
     run.zero();
@@ -527,7 +597,7 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     int q = rank0;  // slot of the segment that the lane's next head closes, plus one
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      const prod_t pi = av[i] * xv[i];
+      const prod_t pi = pr[i];
       if ((hb >> i) & 1u) {
         if (seen) {
           double pv = run.value();
@@ -540,11 +610,6 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
       }
       if (seen) run.add(pi);
       else pre.add(pi);
-    }
-    // ---- the next tile's x gathers go out while this tile finishes
-    if (has_next) {
-#pragma unroll
-      for (int i = 0; i < W; ++i) { xv[i] = (prod_t)x[cn[i]]; av[i] = an[i]; }
     }
     // ---- wave segmented scan of the open segments; carry into each lane
     Acc<DT> inc = seen ? run : pre;
@@ -606,12 +671,11 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
 }
 
 
-// Occupancy asked of the register allocator per instance: the most waves per
-// SIMD each instance reaches without spilling (hipcc's resource report; any
-// higher target spills).  Only FP64 with W = 4 gains from asking (6 instead
-// of 5); the others already run at their spill-free maximum.
+// Occupancy asked of the register allocator per instance: none; every
+// instance already runs at its spill-free maximum (a higher target makes the
+// FP64 W = 4 instance spill).
 template <int DT, int W>
-constexpr int stage1_waves_per_eu() { return (DT == SSS_F64 && W == 4) ? 6 : 1; }
+constexpr int stage1_waves_per_eu() { return 1; }
 
 template <int DT, int W, bool DEBUG>
 __global__ __launch_bounds__(256)
@@ -667,7 +731,7 @@ __global__ void sss_batch_bunch_info(const MatCtx *__restrict__ mats, const int6
 }
 
 // Measurement aid, not part of the method: the memory floor of stage 1's
-// access pattern.  Same tiling, same lane-contiguous col/val loads and the same
+// access pattern.  Same tiling, same grouped col/val loads and the same
 // one-tile-ahead prefetch as stage 1, with no row pass, no segmentation and no
 // partial stores: each lane sums its products (GATHER) or its values plus
 // columns (stream only) and writes one value, so the loads cannot be dropped.
@@ -684,7 +748,7 @@ __device__ __forceinline__ double floor_bunch(const MatCtx &a, const int64_t tb,
   const int64_t SWT = (int64_t)S * WT;
   int cc[W];
   prod_t av[W], xv[W];
-  load_tile<W>(col, val, (int)(tb * SWT), nnz, lane, cc, av);
+  load_tile_g<DT, W>(col, val, (int)(tb * SWT), nnz, lane, cc, av);
 #pragma unroll
   for (int i = 0; i < W; ++i) xv[i] = GATHER ? (prod_t)x[cc[i]] : (prod_t)cc[i];
   double acc = 0.0;
@@ -694,7 +758,7 @@ __device__ __forceinline__ double floor_bunch(const MatCtx &a, const int64_t tb,
     const bool has_next = (t + 1 < S) && (b64 + WT < nnz);
     int cn[W];
     prod_t an[W];
-    if (has_next) load_tile<W>(col, val, (int)b64 + WT, nnz, lane, cn, an);
+    if (has_next) load_tile_g<DT, W>(col, val, (int)b64 + WT, nnz, lane, cn, an);
 #pragma unroll
     for (int i = 0; i < W; ++i) acc += GATHER ? (double)(av[i] * xv[i]) : (double)(av[i] + xv[i]);
     if (has_next) {

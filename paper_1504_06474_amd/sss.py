@@ -83,6 +83,9 @@ def lib():
         L.sss_csr_features.argtypes = [I64, I64, I64, P, I, P, FP]
         L.sss_csr_spmv_autotune.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P, FP, ctypes.POINTER(I)]
         L.sss_floor_probe.argtypes = [P, P, P, P, P, I, P]
+        L.sss_gather_probe.argtypes = [P, P, P, I64, I64, I, I, I, I, I, P, I64, ctypes.POINTER(I64),
+                                       ctypes.POINTER(I), P]
+        L.sss_probe_last_hip_error.restype = ctypes.c_char_p
         L.sss_csr_spmv_stage2_host.argtypes = [P, P, P]
         L.sss_csr_rowwise.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P]
         L.sss_rowwise_last_hip_error.restype = ctypes.c_char_p
@@ -113,7 +116,7 @@ def lib():
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch", "sss_batch_floor_probe",
                   "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_csr_spmv_stage2_host", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
-                  "sss_selector_loaded"):
+                  "sss_selector_loaded", "sss_gather_probe"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -385,6 +388,24 @@ def autotune(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None):
                                        _ptr(val), _ptr(x), _ptr(y), dt, int(reps), _stream(stream), t,
                                        ctypes.byref(best)), "sss_csr_spmv_autotune")
     return np.array(t[:], dtype=np.float64), best.value
+
+
+GATHER_MODES = {0: "vector", 1: "nontemporal", 2: "lds_direct", 3: "buffer_sc1"}
+
+
+def gather_probe(col: torch.Tensor, x: torch.Tensor, out: torch.Tensor, val: Optional[torch.Tensor] = None,
+                 mode: int = 0, unroll: int = 8, waves_per_simd: int = 8, stream=None):
+    """The device's random-gather rate (sss_gather_probe): one nonzero per
+    lane per grid-stride iteration, `unroll` gathers in flight.  Returns
+    (threads, resident workgroups per CU); out needs >= threads entries."""
+    dt = _DTYPES[x.dtype]
+    if val is not None and val.dtype != x.dtype:
+        raise TypeError("val and x must share a type")
+    th, res = ctypes.c_int64(), ctypes.c_int()
+    _check(lib().sss_gather_probe(_ptr(col), _ptr(val), _ptr(x), col.numel(), x.numel(), dt, int(mode), int(unroll),
+                                  int(waves_per_simd), 1 if val is not None else 0, _ptr(out), out.numel(),
+                                  ctypes.byref(th), ctypes.byref(res), _stream(stream)), "sss_gather_probe")
+    return th.value, res.value
 
 
 def csr_rowwise(row_ptr, col, val, x, y, n: int, lanes_per_row: int, stream=None):
