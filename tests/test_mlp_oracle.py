@@ -93,3 +93,53 @@ def test_planted_mistakes_fail_the_difference_check(monkeypatch):
             fd = (mlp.loss(p + e, X, Q) - mlp.loss(p - e, X, Q)) / 2e-6
             worst = max(worst, abs(fd - g[i]))
         assert worst > 1e-4
+
+
+def _hand_network():
+    """A network whose outputs are worked out by hand (exact in binary):
+    layer 1 copies input i to hidden unit i, bias -1 (negative inputs are
+    clipped by the ReLU); layer 2 doubles unit o and adds unit o-1 (not
+    symmetric, so a transposed weight matrix shows), bias 0.5 except -10 for
+    unit 3 (clipped); layer 3 takes 3 x unit o for logit o, minus unit 12 for
+    every logit, bias 0.25 o."""
+    W1 = np.zeros((mlp.N_IN, mlp.N_HID))
+    W1[np.arange(8), np.arange(8)] = 1.0
+    b1 = np.full(mlp.N_HID, -1.0)
+    W2 = np.zeros((mlp.N_HID, mlp.N_HID))
+    W2[np.arange(64), np.arange(64)] = 2.0
+    W2[np.arange(7), np.arange(1, 8)] = 1.0
+    b2 = np.full(mlp.N_HID, 0.5)
+    b2[3] = -10.0
+    W3 = np.zeros((mlp.N_HID, mlp.N_OUT))
+    W3[np.arange(12), np.arange(12)] = 3.0
+    W3[12, :] = -1.0
+    b3 = 0.25 * np.arange(mlp.N_OUT)
+    return mlp.pack([W1, b1, W2, b2, W3, b3])
+
+
+# inputs, and the activations and logits worked out by hand for them
+HAND_X = [[3.0, 0.5, 1.0, -2.0, 2.5, 1.25, 7.0, 0.0], [0.0] * 8]
+HAND_H1 = [[2.0, 0.0, 0.0, 0.0, 1.5, 0.25, 6.0, 0.0], [0.0] * 8]  # units 8.. are 0
+HAND_H2 = [[4.5, 2.5, 0.5, 0.0, 3.5, 2.5, 12.75, 6.5], [0.5, 0.5, 0.5, 0.0, 0.5, 0.5, 0.5, 0.5]]  # units 8.. 0.5
+HAND_Z = [[13.0, 7.25, 1.5, 0.25, 11.0, 8.25, 39.25, 20.75, 3.0, 3.25, 3.5, 3.75],
+          [1.0, 1.25, 1.5, 0.25, 2.0, 2.25, 2.5, 2.75, 3.0, 3.25, 3.5, 3.75]]
+
+
+def test_forward_matches_hand_worked_network():
+    H1, H2, Z = mlp.forward(_hand_network(), np.array(HAND_X))
+    assert np.array_equal(H1[:, :8], HAND_H1) and np.all(H1[:, 8:] == 0.0)
+    assert np.array_equal(H2[:, :8], HAND_H2) and np.all(H2[:, 8:] == 0.5)
+    assert np.array_equal(Z, HAND_Z)
+
+
+@pytest.mark.parametrize("mistake", ["no_relu_1", "no_relu_2", "w2_transposed", "no_bias_2", "bias_3_dropped"])
+def test_forward_planted_mistakes_miss_the_hand_values(mistake):
+    """Each plausible slip in a forward pass changes the hand-worked logits."""
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(_hand_network())
+    X = np.array(HAND_X)
+    a1 = X @ W1 + b1
+    H1 = a1 if mistake == "no_relu_1" else np.maximum(a1, 0.0)
+    a2 = H1 @ (W2.T if mistake == "w2_transposed" else W2) + (0.0 if mistake == "no_bias_2" else b2)
+    H2 = a2 if mistake == "no_relu_2" else np.maximum(a2, 0.0)
+    Z = H2 @ W3 + (0.0 if mistake == "bias_3_dropped" else b3)
+    assert not np.array_equal(Z, HAND_Z)
