@@ -590,29 +590,33 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
       for (int i = 0; i < W; ++i) { xv[i] = (prod_t)x[cn[i]]; av[i] = an[i]; }
     }
     products_in<DT, W>(reinterpret_cast<const prod_t *>(part), lane, pr);
-    Acc<DT> pre, run;
+    // one running sum per lane: before the lane's first head it is the part
+    // of a segment opened in an earlier lane (pre); every later head closes
+    // the segment summed so far, whose partial goes to its LDS slot at once.
+    // At the first head the running sum is staged at that segment's slot
+    // too (q - 1 = rank0 - 1, or 0 for the tile's first entry); the segment's
+    // full sum overwrites it after the wave scan.  The transmitter is added
+    // to the tile's first partial where that partial is read.
+    Acc<DT> acc, pre;
+    acc.zero();
     pre.zero();
-    run.zero();
     bool seen = false;
     int q = rank0;  // slot of the segment that the lane's next head closes, plus one
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      const prod_t pi = pr[i];
       if ((hb >> i) & 1u) {
-        if (seen) {
-          double pv = run.value();
-          if (q == 1) pv += tx;
-          part[q - 1] = pv;
-        }
+        part[q > 0 ? q - 1 : 0] = acc.value();
+        if (!seen) pre = acc;
         seen = true;
         ++q;
-        run.zero();
+        acc.zero();
       }
-      if (seen) run.add(pi);
-      else pre.add(pi);
+      acc.add(pr[i]);
     }
-    // ---- wave segmented scan of the open segments; carry into each lane
-    Acc<DT> inc = seen ? run : pre;
+    if (!seen) pre = acc;
+    // ---- wave segmented scan of the open segments (the lane's running
+    // sum: its run after the last head, or all of it); carry into each lane
+    Acc<DT> inc = acc;
     int f = seen ? 1 : 0;
     wave_seg_scan(inc, f);
     const Acc<DT> carry = dpp_acc<kWaveShr1, 0xf>(inc);
@@ -623,34 +627,34 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     if (seen && rank0 > 0) {
       Acc<DT> c = pre;
       c.prepend(carry);
-      double pv = c.value();
-      if (rank0 == 1) pv += tx;
-      part[rank0 - 1] = pv;
+      part[rank0 - 1] = c.value();
     }
     if (lane == kWave - 1) {
       Acc<DT> c = pre;
       c.prepend(carry);
-      double pv = seen ? run.value() : c.value();
-      if (cnt == 1) pv += tx;
-      part[cnt - 1] = pv;
+      part[cnt - 1] = seen ? acc.value() : c.value();
     }
     __builtin_amdgcn_wave_barrier();
 
-    // ---- coalesced store of the compact partials to y[start + q].  Two
-    // partials stay in double instead: the bunch's first segment goes to the
-    // synchronizer, and the last partial of a tile that ends inside row
-    // `stop` is not stored -- it travels on in the transmitter to the next
-    // tile of the bunch, which stores the row's sum, or, after the bunch's
-    // last tile, to the bunch's tail, which stage 2 adds to the row's
-    // carries before the row's only rounding to y's type.
+    // ---- coalesced store of the compact partials to y[start + q] (the
+    // first with the transmitter added).  Two partials stay in double
+    // instead: the bunch's first segment goes to the synchronizer, and the
+    // last partial of a tile that ends inside row `stop` is not stored -- it
+    // travels on in the transmitter to the next tile of the bunch, which
+    // stores the row's sum, or, after the bunch's last tile, to the bunch's
+    // tail, which stage 2 adds to the row's carries before the row's only
+    // rounding to y's type.
     for (int q = lane; q < cnt; q += kWave) {
       const bool last = (q == cnt - 1);
       const int idx = start + q;
-      if (!(q == 0 && start == r0) && !(last && ends_mid) && (unsigned)idx < (unsigned)m)
-        y_store((y_t)part[q], &y[idx]);
+      if (!(q == 0 && start == r0) && !(last && ends_mid) && (unsigned)idx < (unsigned)m) {
+        double v = part[q];
+        if (q == 0) v += tx;
+        y_store((y_t)v, &y[idx]);
+      }
     }
-    const double p0 = part[0];
-    const double plast = part[cnt - 1];
+    const double p0 = part[0] + tx;
+    const double plast = cnt == 1 ? p0 : part[cnt - 1];
     if (start == r0) sync_v = p0;
     transmitter = ends_mid ? plast : 0.0;
     if (!has_next && ends_mid && !(cnt == 1 && start == r0) && lane == 0) a.tail_val[tb] = plast;
@@ -878,6 +882,8 @@ __device__ __forceinline__ void fixup_dirty(const MatCtx &a, const int64_t tb, Y
   const int n_dirty = __popc(dm);
   if (n_dirty == 0) return;
   // all of the bunch's speculator entries in one load: lane e holds entry e
+  // (loading the slots beside the mask saves a round on bunches with dirty
+  // tiles but costs more on clean ones)
   int2 ent_lane = make_int2(0, 0);
   if (lane < n_dirty) {
     const int4 s = a.speculator[tb * a.S + lane];
@@ -1006,8 +1012,10 @@ __device__ __forceinline__ void fixup_leading(const MatCtx &a, const int64_t fir
 // Stage 2 of one matrix: the first ceil(n_bunches / 64) wavefronts settle the
 // carries of 64 bunches each, the next n_bunches wavefronts re-arrange one
 // bunch's dirty tiles each (separate wavefronts, so the two chains of
-// dependent loads run side by side); all threads share the leading rows.  The
-// three parts write disjoint rows.
+// dependent loads run side by side; a wavefront per bunch measured faster
+// than a resident grid striding over the bunches, even where most bunches
+// are clean); all threads share the leading rows.  The three parts write
+// disjoint rows.
 template <typename YT>
 __global__ __launch_bounds__(1024) void sss_fixup(MatCtx a) {
   extern __shared__ unsigned char lds_raw[];
