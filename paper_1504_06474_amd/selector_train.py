@@ -2,6 +2,13 @@
 
     python -m paper_1504_06474_amd.selector_train --out <out-dir> \
         [--train 2000] [--test 200] [--reps 5] [--steps 4000]
+    python -m paper_1504_06474_amd.selector_train --out <out-dir> --collect A:B
+    python -m paper_1504_06474_amd.selector_train --out <out-dir> --fit
+
+The first form does everything in one process.  --collect A:B times
+matrices A..B-1 only and saves them as <out-dir>/part_A_B.npz (the timing
+can then span several processes); --fit trains and evaluates from every part
+file in <out-dir>.
 
 1. Data: matrices 0..train+test-1 of the selector set (2D 5-point and 3D
    27-point stencils, FEM-like bands, web-like lognormal rows, dense rows in a
@@ -193,13 +200,30 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dtypes", default="f64,f32,bf16", help="value types to time each matrix in")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--collect", default="", help="A:B -- time matrices A..B-1 only, save part_A_B.npz")
+    ap.add_argument("--fit", action="store_true", help="train and evaluate from the part files in --out")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     sss.lib()
     n_all = args.train + args.test
     dtypes = tuple(args.dtypes.split(","))
-    log(f"[selector] timing {n_all} matrices x {dtypes}, {sss.N_CLASSES} classes, {args.reps} runs per trial")
-    feats, times, t_def, names, kinds, mats, sizes = collect(range(n_all), args.reps, dtypes)
+    keys = ("feats", "times", "t_default", "names", "kinds", "mats", "sizes")
+    if args.collect:
+        a, b = (int(v) for v in args.collect.split(":"))
+        log(f"[selector] timing matrices {a}..{b - 1} x {dtypes}, {sss.N_CLASSES} classes, {args.reps} runs per trial")
+        arrays = collect(range(a, b), args.reps, dtypes)
+        np.savez(os.path.join(args.out, f"part_{a}_{b}.npz"), **dict(zip(keys, arrays)))
+        log(f"[selector] saved part_{a}_{b}.npz")
+        return
+    if args.fit:
+        import glob
+        parts = [np.load(f) for f in sorted(glob.glob(os.path.join(args.out, "part_*.npz")))]
+        feats, times, t_def, names, kinds, mats, sizes = (np.concatenate([p[k] for p in parts]) for k in keys)
+        if sorted(set(mats.tolist())) != list(range(n_all)):
+            raise SystemExit(f"the part files cover {len(set(mats.tolist()))} of matrices 0..{n_all - 1}")
+    else:
+        log(f"[selector] timing {n_all} matrices x {dtypes}, {sss.N_CLASSES} classes, {args.reps} runs per trial")
+        feats, times, t_def, names, kinds, mats, sizes = collect(range(n_all), args.reps, dtypes)
     np.savez(os.path.join(args.out, "dataset.npz"), feats=feats, times=times, t_default=t_def, names=names,
              kinds=kinds, mats=mats, sizes=sizes)
     tr, te = mats < args.train, mats >= args.train

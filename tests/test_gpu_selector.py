@@ -76,7 +76,7 @@ def test_selector_gain_on_held_out(sel, kind):
     r = float(np.exp(np.mean(np.log(regrets)))) - 1
     note(f"  geomean gain over default {g:.3f}, regret vs grid {r:.4f}")
     assert g > 1.1
-    assert r < 0.10
+    assert r <= 0.05  # the selector's target: within 5% of the autotuned grid
 
 
 def test_grid_plan(sel):
