@@ -380,6 +380,158 @@ def reduced_on_benchmark_matrix(torch, sss, A, x, ms_f64: float, steps: int, war
     return out
 
 
+def events_us(torch, fn, copies, steps: int, warmup: int) -> float:
+    """Average microseconds of fn(copy) over `steps` launches rotating the
+    copies, between two events on the current stream."""
+    for k in range(warmup):
+        fn(copies[k % len(copies)])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        fn(copies[k % len(copies)])
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps * 1e3
+
+
+# the probe configurations timed by gather_ceiling: (mode, in flight, waves
+# per SIMD); mode 0 plain loads over the whole grid as one front, 4 the same
+# with one contiguous chunk per wavefront, 2 direct-to-LDS gathers
+PROBE_CONFIGS = [(0, 1, 4), (0, 4, 4), (0, 16, 4), (0, 16, 8), (0, 2, 2), (4, 4, 4), (4, 16, 2), (4, 8, 1),
+                 (2, 1, 4), (2, 8, 1)]
+
+
+def gather_ceiling(torch, sss, copies, alg: int, steps: int, warmup: int) -> dict:
+    """The device's rate for the reads of a CSR SpMV on this matrix with
+    none of the method's choices (sss_gather_probe with val streamed: col and
+    val coalesced, x gathered), over a set of issue modes, depths and
+    occupancies; the best reading is the design-independent ceiling."""
+    xdt = copies[0][3].dtype
+    out_buf = torch.empty(1 << 20, dtype=xdt, device="cuda")
+    res = {}
+    for mode, U, wps in PROBE_CONFIGS:
+        try:
+            sss.gather_probe(copies[0][1], copies[0][3], out_buf, copies[0][2] if copies[0][2].dtype == xdt else None,
+                             mode, U, wps)
+        except sss.SSSError:
+            continue
+        us = events_us(torch, lambda c: sss.gather_probe(c[1], c[3], out_buf, c[2], mode, U, wps), copies,
+                       steps, warmup)
+        res[f"{sss.GATHER_MODES[mode & 3]}{'_chunked' if mode & 4 else ''}_u{U}_w{wps}"] = round(us, 2)
+    del out_buf
+    best = min(res, key=res.get)
+    return {"probe_us": res, "best": best, "best_us": res[best],
+            "best_alg_GBps": round(alg / (res[best] * 1e-6) / 1e9, 1),
+            "best_frac_of_peak": round(alg / (res[best] * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4)}
+
+
+def stencil_block(torch, sss, steps: int, warmup: int) -> dict:
+    """Where gathers are cheap: the 27-point stencil on a 160^3 grid (4.1M
+    rows, 109M nnz, 1.39 GB in FP64: far past the 256 MB last-level cache, so
+    one copy streams from HBM every call).  The selector's plan and the
+    default plan, stage 1 against the floor of its own access pattern, the
+    design-independent probe, and the fraction of the HBM peak."""
+    from csrgen.torch_gen import _stencil
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    d = _stencil(160, 3, gen, "cuda")
+    m, nnz = d["m"], d["nnz"]
+    c = (d["row_ptr"], d["col"], d["val"], d["x"], torch.empty(m, dtype=torch.float64, device="cuda"))
+    copies = [c]
+    alg = alg_bytes(m, m, nnz, 8, 8)
+    out = {"workload": "stencil3d_160_f64", "m": m, "nnz": nnz, "alg_bytes": alg}
+    # the exact product on sampled rows, to check each plan's timed output
+    rows = np.random.default_rng(7).choice(m, size=2000, replace=False)
+    rp = d["row_ptr"].cpu().numpy().astype(np.int64)
+    colh, valh, xh = d["col"].cpu().numpy(), d["val"].cpu().numpy(), d["x"].cpu().numpy()
+    idx = np.concatenate([np.arange(rp[r], rp[r + 1]) for r in rows])
+    sub = np.zeros(rows.size + 1, dtype=np.int64)
+    np.cumsum(rp[rows + 1] - rp[rows], out=sub[1:])
+    ref, sc = row_sums(sub, colh[idx], valh[idx], xh)
+    ok = True
+    for name, kw in (("selected", {"mode": sss.MODE_SELECTOR}), ("default", {})):
+        if name == "selected" and not sss.load_selector():
+            continue
+        ps = PlanSet(sss, copies, m, m, nnz, True, dtype=torch.float64, **kw)
+        info = ps.info()
+        ex = events_us(torch, lambda cc: ps.execute(*cc), copies, steps, warmup)
+        got = c[4].cpu().numpy()[rows]
+        ok = ok and bool(np.all(np.abs(got - ref) <= 1e-12 * sc))
+        s1 = events_us(torch, lambda cc: ps.stage1(*cc), copies, steps, warmup)
+        s2 = events_us(torch, lambda cc: ps.stage2(cc[0], cc[4]), copies, steps, warmup)
+        fo = torch.empty(info["n_bunches"] * 64, dtype=torch.float64, device="cuda")
+        fs = events_us(torch, lambda cc: ps.floor_probe(cc[1], cc[2], cc[3], fo, False), copies, steps, warmup)
+        fg = events_us(torch, lambda cc: ps.floor_probe(cc[1], cc[2], cc[3], fo, True), copies, steps, warmup)
+        del fo
+        out[name] = {"W": info["W"], "S": info["S"], "execute_us": round(ex, 2), "stage1_us": round(s1, 2),
+                     "stage2_us": round(s2, 2), "floor_stream_us": round(fs, 2), "floor_stream_gather_us": round(fg, 2),
+                     "stage1_frac_of_floor": round(fg / s1, 3),
+                     "execute_alg_GBps": round(alg / (ex * 1e-6) / 1e9, 1),
+                     "execute_frac_of_peak": round(alg / (ex * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4),
+                     "stage1_frac_of_peak": round(alg / (s1 * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4)}
+        ps.close()
+    out["gather_ceiling"] = gather_ceiling(torch, sss, copies, alg, steps, warmup)
+    out["sampled_rows_within_1e-12"] = ok
+    log(f"[bench] stencil: {out}")
+    del d, c, copies
+    torch.cuda.empty_cache()
+    return out
+
+
+def classes_block(torch, sss, steps: int, warmup: int) -> dict:
+    """Bandwidth utilisation per matrix class (the paper's Section 4.4
+    bandwidth figure, and its Section 4.5 parameter sweeps): one large matrix
+    of every selector class, FP64, enough rotated copies to pass 1 GB, the
+    selector's plan: time, algorithmic GB/s and fraction of the 8 TB/s peak,
+    stage 1 against the floor of its access pattern and against the
+    design-independent probe; and every (W, S) class timed on it."""
+    from csrgen.torch_gen import _stencil, _fem_band, _weblike, _dense_rows
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    rng = np.random.default_rng(11)
+    mats = {
+        "stencil2d": lambda: _stencil(1414, 2, gen, "cuda"),
+        "stencil3d": lambda: _stencil(125, 3, gen, "cuda"),
+        "fem_band": lambda: _fem_band(2_000_000, gen, "cuda"),
+        "weblike": lambda: _weblike(2_000_000, gen, "cuda"),
+        "dense_rows": lambda: _dense_rows(1_000_000, gen, "cuda", 8, rng.integers(10_000, 1_000_000, size=8)),
+    }
+    out = {}
+    for cls, make in mats.items():
+        d = make()
+        m, n, nnz = d["m"], d["n"], d["nnz"]
+        alg = alg_bytes(m, n, nnz, 8, 8)
+        k = max(1, int(np.ceil((1 << 30) / alg)))
+        copies = [(d["row_ptr"], d["col"], d["val"], d["x"], torch.empty(m, dtype=torch.float64, device="cuda"))]
+        for _ in range(k - 1):
+            copies.append(tuple(t.clone() for t in copies[0][:4]) + (torch.empty(m, dtype=torch.float64, device="cuda"),))
+        ps = PlanSet(sss, copies, m, n, nnz, True, dtype=torch.float64, mode=sss.MODE_SELECTOR)
+        info = ps.info()
+        ex = events_us(torch, lambda cc: ps.execute(*cc), copies, steps, warmup)
+        s1 = events_us(torch, lambda cc: ps.stage1(*cc), copies, steps, warmup)
+        fo = torch.empty(info["n_bunches"] * 64, dtype=torch.float64, device="cuda")
+        fg = events_us(torch, lambda cc: ps.floor_probe(cc[1], cc[2], cc[3], fo, True), copies, steps, warmup)
+        del fo
+        ceil = gather_ceiling(torch, sss, copies, alg, max(5, steps // 2), 2)
+        grid, best = sss.autotune(*copies[0], n=n, reps=5)
+        out[cls] = {"m": m, "nnz": nnz, "alg_bytes": alg, "copies_rotated": k, "W": info["W"], "S": info["S"],
+                    "execute_us": round(ex, 2), "stage1_us": round(s1, 2),
+                    "alg_GBps": round(alg / (ex * 1e-6) / 1e9, 1),
+                    "frac_of_peak": round(alg / (ex * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4),
+                    "stage1_frac_of_own_floor": round(fg / s1, 3),
+                    "stage1_frac_of_probe_ceiling": round(ceil["best_us"] / s1, 3),
+                    "probe_ceiling_frac_of_peak": ceil["best_frac_of_peak"],
+                    "grid_us_by_class": {f"W{sss.class_params(c)[0]}S{sss.class_params(c)[1]}": round(float(t), 2)
+                                         for c, t in enumerate(grid)},
+                    "grid_best": "W{}S{}".format(*sss.class_params(best))}
+        log(f"[bench] class {cls}: {out[cls]}")
+        ps.close()
+        del copies, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def host_stage2_block(torch, sss, plan, copies, A, x, reps: int = 20) -> dict:
     """The paper's split on this discrete GPU: stage 1 on the device, y and
     the plan's small arrays to host memory, stage 2 on one host core, y back;
@@ -535,6 +687,25 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
             if nz.any():
                 worst_grid = max(worst_grid, float((err[nz] / sc[nz]).max()))
         bp_grid.close()
+        # the learned selector's per-matrix schedule (W by its votes, each
+        # matrix its own S)
+        sel_rec = None
+        if sss.load_selector():
+            bp_sel = sss.BatchPlan(dev, dtype=tdt, mode=sss.MODE_SELECTOR)
+            sW, sS = bp_sel.schedule()
+            ms_sel = timed(bp_sel.execute, steps)
+            ms_sel_graph = timed(bp_sel.graph_launch, steps)
+            worst_sel = 0.0
+            for (A, x), d, ref, sc in zip(mats, dev, refs, scales):
+                err = np.abs(d[4].double().cpu().numpy() - ref)
+                nz = sc > 0
+                if nz.any():
+                    worst_sel = max(worst_sel, float((err[nz] / sc[nz]).max()))
+            bp_sel.close()
+            sel_rec = {"W": sW, "S_counts": {str(k): int(sum(1 for v in sS if v == k)) for k in (1, 2, 4, 8)},
+                       "batched_us": round(ms_sel * 1e3, 1), "batched_graph_us": round(ms_sel_graph * 1e3, 1),
+                       "speedup_vs_separate": round(ms_sep / ms_sel, 2),
+                       "vs_autotuned_grid": round(ms_grid / ms_sel, 3), "max_err_scaled_vs_f64": worst_sel}
         vb = 8 if kind == "f64" else 4
         byts = sum(alg_bytes(A.m, A.n, A.nnz, vb, vb) for A, _ in mats)
         out[kind] = {"W": info["W"], "S": info["S"], "n_bunches": info["n_bunches"],
@@ -552,7 +723,8 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
                                    "batched_graph_us": round(ms_grid_graph * 1e3, 1),
                                    "speedup_vs_separate": round(ms_sep / ms_grid, 2),
                                    "speedup_vs_separate_graph": round(ms_sep_graph / ms_grid, 2),
-                                   "max_err_scaled_vs_f64": worst_grid}}
+                                   "max_err_scaled_vs_f64": worst_grid},
+                     "selector_scheduled": sel_rec}
         log(f"[bench] batched {kind}: {out[kind]}")
         del g, plans, bp, dev
         torch.cuda.synchronize()
@@ -664,6 +836,11 @@ def main():
     ap.add_argument("--skip-batched", action="store_true", help="skip the 512-matrix batched comparison")
     ap.add_argument("--skip-selector", action="store_true", help="skip the tile-selector evaluation")
     ap.add_argument("--skip-cg", action="store_true", help="skip the conjugate-gradient workload")
+    ap.add_argument("--skip-stencil", action="store_true", help="skip the 1.39 GB stencil block")
+    ap.add_argument("--skip-classes", action="store_true", help="skip the per-class bandwidth block")
+    ap.add_argument("--plan", choices=["grid", "selector", "default"], default="grid",
+                    help="the headline plan's (W, S): the library's grid autotuner (GRID plans), the learned "
+                         "selector (SELECTOR plans) or the per-type default; --W/--S fix them instead")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -693,12 +870,26 @@ def main():
         copies.append((torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col).to(dev),
                        torch.from_numpy(A.val).to(dev), torch.from_numpy(x).to(dev),
                        torch.empty(m, dtype=torch.float64, device=dev)))
-    # plan / analyse (outside the timed region): with bind_rows the tile
-    # boundary search runs once here instead of in every call
+    # plan / analyse (outside the timed region): the parameters from the
+    # learned selector (SELECTOR mode: features on the device, the network),
+    # or the default, or the fixed --W/--S; with bind_rows the tile boundary
+    # search runs once here instead of in every call
     bind = not args.no_bind_rows
-    plan = PlanSet(sss, copies, m, n, nnz, bind, dtype=torch.float64, W=args.W, S=args.S, B=args.B)
+    plan_name = "fixed" if (args.W or args.S) else args.plan
+    if plan_name == "selector" and not sss.load_selector():
+        plan_name = "default"
+    plan_kw = {"W": args.W, "S": args.S}
+    if plan_name == "selector":
+        plan_kw = {"mode": sss.MODE_SELECTOR}
+    elif plan_name == "grid":
+        # the autotuner's timing of every class on this matrix (what a GRID
+        # plan does), then one bound plan of that class per rotated copy
+        _, best = sss.autotune(*copies[0], n=n, reps=5)
+        W_g, S_g = sss.class_params(best)
+        plan_kw = {"W": W_g, "S": S_g}
+    plan = PlanSet(sss, copies, m, n, nnz, bind, dtype=torch.float64, B=args.B, **plan_kw)
     info = plan.info()
-    log(f"[bench] plan {info}")
+    log(f"[bench] plan ({plan_name}) {info}")
     torch.cuda.synchronize()
 
     def step(k):
@@ -782,7 +973,7 @@ def main():
     # the other plan variant (first rows searched in every call, or bound)
     ms_other = s1_other = float("nan")
     if not args.skip_extras:
-        other = PlanSet(sss, copies, m, n, nnz, not bind, dtype=torch.float64, W=args.W, S=args.S, B=args.B)
+        other = PlanSet(sss, copies, m, n, nnz, not bind, dtype=torch.float64, W=info["W"], S=info["S"], B=args.B)
         ms_other = time_steps(torch, other, copies, args.steps, args.warmup)
         torch.cuda.synchronize()
         for k in range(args.steps):
@@ -796,6 +987,25 @@ def main():
         other.close()
         log(f"[bench] {'searching' if bind else 'bound-rows'} plan: {ms_other * 1e3:.2f} us/step, "
             f"stage1 {s1_other * 1e3:.2f} us")
+
+    # the per-type default plan (the paper's Table 3 values for its AMD GPU)
+    # beside the headline plan, and the device's gather ceiling on this matrix
+    default_rec = ceiling = None
+    if not args.skip_extras:
+        dp = PlanSet(sss, copies, m, n, nnz, bind, dtype=torch.float64, B=args.B)
+        dinfo = dp.info()
+        default_rec = {"W": dinfo["W"], "S": dinfo["S"],
+                       "us_per_step": round(events_us(torch, lambda c: dp.execute(*c), copies, args.steps,
+                                                      args.warmup), 2),
+                       "stage1_us": round(events_us(torch, lambda c: dp.stage1(*c), copies, args.steps,
+                                                    args.warmup), 2)}
+        for c in copies:  # restore every copy's y to a full product of the headline plan
+            plan.execute(*c)
+        dp.close()
+        log(f"[bench] default plan: {default_rec}")
+        ceiling = gather_ceiling(torch, sss, copies, alg_bytes(m, n, nnz, 8, 8), args.steps, args.warmup)
+        ceiling["stage1_frac_of_ceiling"] = round(ceiling["best_us"] / (s1_ms * 1e3), 3)
+        log(f"[bench] gather ceiling: {ceiling}")
 
     # the paper's comparison (Section 4.3) on this matrix: row-wise kernels
     comp_c2 = None
@@ -851,8 +1061,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "powerlaw_1M_zipf2_f64", "m": m, "n": n, "nnz": nnz, "W": info["W"],
-                   "S": info["S"], "B": info["B"], "T": 64, "bind_rows": bind, "copies_rotated": len(copies)},
+        "config": {"workload": "powerlaw_1M_zipf2_f64", "m": m, "n": n, "nnz": nnz, "plan": plan_name,
+                   "W": info["W"], "S": info["S"], "B": info["B"], "T": 64, "bind_rows": bind,
+                   "copies_rotated": len(copies)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": measured_traffic(info["W"], info["S"], info["B"], bind),
@@ -870,6 +1081,8 @@ def main():
             "warm_cache_us_per_step": round(ms_warm * 1e3, 2),
             "warm_cache_GFLOPs": round(2.0 * nnz / (ms_warm * 1e-3) / 1e9, 2),
             "paper_formula_GBps": round(paper_bytes(m, nnz, 8) / (ms_step * 1e-3) / 1e9, 1),
+            "default_plan": default_rec,
+            "gather_ceiling": ceiling,
             "floors": None if args.skip_extras else {"stream_us": round(floors["stream_us"], 2),
                        "stream_GBps": round(12.0 * nnz / (floors["stream_us"] * 1e-6) / 1e9, 1),
                        "stream_gather_us": round(floors["stream_gather_us"], 2),
@@ -891,6 +1104,10 @@ def main():
         out["extras"]["batched"] = batched_block(torch, sss, min(args.steps, 20), 2)
     if not args.skip_cg:
         out["extras"]["cg"] = cg_block(torch, sss)
+    if not args.skip_stencil:
+        out["extras"]["stencil"] = stencil_block(torch, sss, min(args.steps, 50), min(args.warmup, 5))
+    if not args.skip_classes:
+        out["extras"]["classes"] = classes_block(torch, sss, min(args.steps, 30), min(args.warmup, 3))
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, x, args.cpu_seconds)

@@ -235,11 +235,21 @@ typedef struct {
  * for rows (Section 3.2).  Stage 1 runs one wavefront per bunch, each XCD
  * taking a contiguous run of the bunch space (opts->batch_persistent: a
  * persistent grid instead); stage 2 is a persistent grid.  All matrices
- * share dtype and W (opts); each
- * may set its own S.  The descriptors' pointers are bound to the plan: the
- * plan must be recreated if a matrix or vector moves.  Different matrices
- * must not share y storage.  Allocates (the descriptors, prefix arrays and
- * every matrix's synchronizer/speculator) and synchronises. */
+ * share dtype and W; each may have its own S.
+ * FIXED mode (opts NULL or mode FIXED): W = opts->W (0: the type's default),
+ * each matrix's S = its descriptor's S, else opts->S, else the default.
+ * SELECTOR mode: the tile schedule comes from the loaded selector network
+ * (sss_selector_set; the type's defaults when none is loaded): each matrix's
+ * features (sss_csr_features), with the three size features (rows, columns,
+ * nonzeros) replaced by the batch's totals -- one grid runs the bunches of
+ * all matrices, so how well a schedule fills the device depends on the whole
+ * launch -- are scored (sss_selector_scores); W is
+ * opts->W if given, else the W of the class picked for most nonzeros of the
+ * batch; each matrix then takes the S of its best-scored class with that W
+ * (descriptors' S are ignored).  The descriptors' pointers are bound to the
+ * plan: the plan must be recreated if a matrix or vector moves.  Different
+ * matrices must not share y storage.  Allocates (the descriptors, prefix
+ * arrays and every matrix's synchronizer/speculator) and synchronises. */
 int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, const sss_plan_opts *opts,
                           void *stream, sss_plan *out);
 
@@ -253,6 +263,11 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
  * overwritten.  Allocates and synchronises. */
 int sss_batch_plan_create_grid(int count, const sss_csr_desc *mats, sss_dtype dt, int reps, void *stream,
                                float *class_us, int *best_class, sss_plan *out);
+
+/* A batch plan's tile schedule (host call): its W, and each matrix's S in
+ * HOST S[count] (count must be the plan's matrix count).  Either may be
+ * NULL. */
+int sss_batch_plan_schedule(sss_plan p, int count, int *W, int *S);
 
 /* Run a batch plan on `stream`: two launches (stage 1, stage 2), no
  * allocation, no host synchronisation. */
@@ -417,6 +432,12 @@ int sss_selector_set(const float *params, const float *mean, const float *stdv);
 /* Class the loaded selector picks for HOST features[8] (forward kernels on the
  * device, synchronous).  SSS_ERR_UNSUPPORTED if no selector is loaded. */
 int sss_selector_predict(const float *feats, int *cls);
+
+/* The loaded selector's 12 class scores (logits, HOST float[12]) for HOST
+ * features[8]; the class it picks is the largest.  Batch plans in SELECTOR
+ * mode use them to pick each matrix's S among the classes of the batch's W.
+ * SSS_ERR_UNSUPPORTED if no selector is loaded. */
+int sss_selector_scores(const float *feats, float *logits);
 
 /* 1 if a selector is loaded on the current device. */
 int sss_selector_loaded(void);

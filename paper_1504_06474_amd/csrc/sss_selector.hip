@@ -350,6 +350,24 @@ int sss_selector_set(const float *params, const float *mean, const float *stdv) 
   return SSS_OK;
 }
 
+int sss_selector_scores(const float *feats, float *logits) {
+  if (!feats || !logits) return SSS_ERR_INVALID_VALUE;
+  int dev = 0;
+  SEL_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SSS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  SelectorState &st = g_sel[dev];
+  if (!st.loaded) return SSS_ERR_UNSUPPORTED;
+  float x[kIn];
+  for (int i = 0; i < kIn; ++i) x[i] = (feats[i] - st.mean[i]) / (st.stdv[i] > 0.f ? st.stdv[i] : 1.f);
+  float *dX = st.d_work, *dH1 = dX + kIn, *dH2 = dH1 + kHid, *dZ = dH2 + kHid;
+  SEL_HIP(hipMemcpy(dX, x, sizeof(x), hipMemcpyHostToDevice));
+  const int rc = forward_launch(st.d_params, dX, 1, dH1, dH2, dZ, nullptr);
+  if (rc != SSS_OK) return rc;
+  SEL_HIP(hipMemcpy(logits, dZ, sizeof(float) * kOut, hipMemcpyDeviceToHost));
+  return SSS_OK;
+}
+
 int sss_selector_predict(const float *feats, int *cls) {
   if (!feats || !cls) return SSS_ERR_INVALID_VALUE;
   int dev = 0;

@@ -53,6 +53,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <climits>
 #include <cstdint>
 #include <cstring>
@@ -930,12 +931,14 @@ __device__ __forceinline__ void fixup_dirty(const MatCtx &a, const int64_t tb, Y
 // exactly where the run's first bunch begins, the part of r computed before
 // the run is the tail of the bunch before the run (double), added first; y[r]
 // is rounded to its type only here.  Runs of up to kShortRun bunches are
-// summed by the run's first lane in bunch order; longer runs (rows longer than
-// kShortRun bunches) by the whole wavefront: coalesced loads, per-lane partial
-// sums, then a fixed-shape tree over the lanes, so the rounding does not
-// depend on timing.
+// summed by the run's first lane in bunch order, from this chunk's entries
+// and the kShortRun after it staged in the wavefront's LDS (`lds`: at least
+// (64 + kShortRun) * 12 bytes; register arrays for that look-ahead would cap
+// the kernel's occupancy); longer runs (rows longer than kShortRun bunches)
+// by the whole wavefront: coalesced loads, per-lane partial sums, then a
+// fixed-shape tree over the lanes, so the rounding does not depend on timing.
 template <typename YT>
-__device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chunk0, const int lane) {
+__device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chunk0, const int lane, void *lds) {
   const int32_t *__restrict__ rp = a.row_ptr;
   YT *y = static_cast<YT *>(a.y);
   const int64_t SWT = (int64_t)a.S * a.W * kWave;
@@ -943,8 +946,8 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
   const int64_t tb = chunk0 + lane;
   const bool valid = tb < nb;
   // one round of loads: this chunk's entries, the kShortRun entries after it
-  // (lanes 0..kShortRun-1) and the one before it; every look-ahead below is a
-  // lane shuffle.  Entries past the last bunch read as index -1, value 0.
+  // (lanes 0..kShortRun-1) and the one before it.  Entries past the last
+  // bunch read as index -1, value 0.
   const int idx = valid ? a.sync_idx[tb] : -1;
   const double own_v = valid ? a.sync_val[tb] : 0.0;
   const int64_t tt = chunk0 + kWave + lane;
@@ -952,30 +955,29 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
   const int tail_i = tail_in ? a.sync_idx[tt] : -1;
   const double tail_v = tail_in ? a.sync_val[tt] : 0.0;
   const int before_chunk = chunk0 > 0 ? a.sync_idx[chunk0 - 1] : -1;
-  int idn[kShortRun + 1];  // sync_idx[tb + j]
-  double vv[kShortRun];    // sync_val[tb + j]
-#pragma unroll
-  for (int j = 0; j <= kShortRun; ++j) {
-    const int src = lane + j;
-    const int from_own = __shfl(idx, src & (kWave - 1), kWave);
-    const int from_tail = __shfl(tail_i, (src - kWave) & (kWave - 1), kWave);
-    idn[j] = src < kWave ? from_own : from_tail;
-    if (j < kShortRun) {
-      const double vo = __shfl(own_v, src & (kWave - 1), kWave);
-      const double vt = __shfl(tail_v, (src - kWave) & (kWave - 1), kWave);
-      vv[j] = src < kWave ? vo : vt;
-    }
+  double *s_val = static_cast<double *>(lds);
+  int *s_idx = reinterpret_cast<int *>(s_val + kWave + kShortRun);
+  s_idx[lane] = idx;
+  s_val[lane] = own_v;
+  if (lane < kShortRun) {
+    s_idx[kWave + lane] = tail_i;
+    s_val[kWave + lane] = tail_v;
   }
+  // one wavefront owns `lds` and its LDS operations run in order
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   int prev = __shfl(idx, (lane + kWave - 1) & (kWave - 1), kWave);
   if (lane == 0) prev = before_chunk;
   const bool head = valid && (tb == 0 || prev != idx);
-  const bool is_long = head && (tb + kShortRun < nb) && (idn[kShortRun] == idx);
+  const bool is_long = head && (tb + kShortRun < nb) && (s_idx[lane + kShortRun] == idx);
   if (head && !is_long) {
-    // sync_idx is non-decreasing: the run is a prefix of the next kShortRun
+    // sync_idx is non-decreasing (entries past the end read -1): the run is
+    // the prefix of the next kShortRun entries equal to idx
     double sum = 0.0;
-#pragma unroll
-    for (int j = 0; j < kShortRun; ++j)
-      if (idn[j] == idx) sum += vv[j];
+    for (int j = 0; j < kShortRun; ++j) {
+      if (s_idx[lane + j] != idx) break;
+      sum += s_val[lane + j];
+    }
     const bool fresh = (int64_t)rp[idx] == tb * SWT;
     y[idx] = (YT)(fresh ? sum : a.tail_val[tb - 1] + sum);
   }
@@ -998,6 +1000,9 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
       y[ridx] = (YT)(fresh ? total : a.tail_val[t0 - 1] + total);
     }
   }
+  // the staged entries are read before the wavefront's next use of `lds`
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // (3) rows before the first tile's start row are empty and covered by no
@@ -1024,7 +1029,7 @@ __global__ __launch_bounds__(1024) void sss_fixup(MatCtx a) {
   YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
   const int64_t n_chunks = (a.n_bunches + kWave - 1) / kWave;
-  if (wave < n_chunks) fixup_carries<YT>(a, wave * kWave, lane);
+  if (wave < n_chunks) fixup_carries<YT>(a, wave * kWave, lane, slots);
   else if (wave < n_chunks + a.n_bunches) fixup_dirty<YT>(a, wave - n_chunks, slots, lane);
   fixup_leading<YT>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
@@ -1043,7 +1048,8 @@ __global__ __launch_bounds__(1024) void sss_fixup_batch(BatchArgs b) {
     if (w < b.total_chunks) {
       const int i = (int)wave_rightmost(b.chunk_base, (int64_t)b.count, w, lane);
       const MatCtx a = b.mats[i];
-      fixup_carries<YT>(a, (w - b.chunk_base[i]) * kWave, lane);
+      fixup_carries<YT>(a, (w - b.chunk_base[i]) * kWave, lane,
+                        reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave);
     } else if (w < b.total_chunks + b.total_bunches) {
       const int64_t g = w - b.total_chunks;
       const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane);
@@ -1086,6 +1092,9 @@ constexpr int kDefaultB = 2;
 #endif
 constexpr int kFixupThreads = SSS_FIXUP_THREADS;
 constexpr size_t kFixupLdsBytes = 64 * 1024;  // LDS of one fixup workgroup
+// a stage-2 wavefront's LDS (W * 64 y values, W >= 4, y at least 4 bytes)
+// also holds the carry pass's staged entries
+static_assert(4 * kWave * 4 >= (kWave + kShortRun) * (sizeof(double) + sizeof(int)), "carry staging fits");
 constexpr int kMaxS = 16;
 
 bool dtype_ok(int dt) { return dt == SSS_F64 || dt == SSS_F32 || dt == SSS_BF16; }
@@ -1166,6 +1175,7 @@ struct sss_plan_s {
   bool batch = false;
   bool batch_persistent = false;
   BatchArgs bargs{};
+  std::vector<int> mat_S;  // each matrix's tiles per thread-bunch
   int blocks1 = 0, blocks2 = 0, wpb2 = 1;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -1712,14 +1722,59 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   if (!out || count < 0 || (count > 0 && !mats)) return SSS_ERR_INVALID_VALUE;
   *out = nullptr;
   if (!dtype_ok(dt)) return SSS_ERR_UNSUPPORTED;
-  sss_plan_opts o = {SSS_MODE_FIXED, 0, 0, 0, 0};
+  sss_plan_opts o{};
+  o.mode = SSS_MODE_FIXED;
   if (opts) o = *opts;
-  if (o.mode != SSS_MODE_FIXED) return SSS_ERR_UNSUPPORTED;
-  const int W = o.W ? o.W : default_W(dt);
+  if (o.mode != SSS_MODE_FIXED && o.mode != SSS_MODE_SELECTOR) return SSS_ERR_UNSUPPORTED;
+  int W = o.W ? o.W : default_W(dt);
   const int S = o.S ? o.S : default_S(dt);
   const int B = o.B ? o.B : kDefaultB;
   if (!(W == 4 || W == 8 || W == 16)) return SSS_ERR_UNSUPPORTED;
   if (S < 1 || S > kMaxS || B < 1 || B > 4 || o.debug) return SSS_ERR_INVALID_VALUE;
+  // SELECTOR mode: every matrix's S from its class scores, W shared
+  std::vector<int> sel_S;
+  if (o.mode == SSS_MODE_SELECTOR && count > 0 && sss_selector_loaded()) {
+    for (int i = 0; i < count; ++i)
+      if (mats[i].m < 0 || mats[i].n < 0 || mats[i].nnz < 0 || mats[i].m > SSS_MAX_INDEX ||
+          mats[i].n > SSS_MAX_INDEX || mats[i].nnz > SSS_MAX_INDEX || (mats[i].m > 0 && !mats[i].row_ptr))
+        return SSS_ERR_INVALID_VALUE;
+    std::vector<float> scores((size_t)count * SSS_N_CLASSES, 0.f);
+    double w_votes[17] = {};
+    // a matrix is scored with its own row-structure features but the size
+    // features of the whole launch: the batch's bunches share one grid, so
+    // how well a tile schedule fills the device depends on the total work,
+    // not on the one matrix
+    double tot_m = 0, tot_n = 0, tot_nnz = 0;
+    for (int i = 0; i < count; ++i) { tot_m += (double)mats[i].m; tot_n += (double)mats[i].n; tot_nnz += (double)mats[i].nnz; }
+    for (int i = 0; i < count; ++i) {
+      const sss_csr_desc &d = mats[i];
+      if (d.m == 0 || d.nnz == 0) continue;
+      float f[SSS_N_FEATURES];
+      int rc = sss_csr_features(d.m, d.n, d.nnz, d.row_ptr, dt, stream, f);
+      f[0] = (float)std::log2(tot_m + 1.0);
+      f[1] = (float)std::log2(tot_n + 1.0);
+      f[2] = (float)std::log2(tot_nnz + 1.0);
+      if (rc == SSS_OK) rc = sss_selector_scores(f, &scores[(size_t)i * SSS_N_CLASSES]);
+      if (rc != SSS_OK) return rc;
+      const float *z = &scores[(size_t)i * SSS_N_CLASSES];
+      const int best = (int)(std::max_element(z, z + SSS_N_CLASSES) - z);
+      int Wc = 0, Sc = 0;
+      (void)sss_class_params(best, &Wc, &Sc);
+      w_votes[Wc] += (double)d.nnz;
+    }
+    if (!o.W) W = w_votes[4] > w_votes[8] && w_votes[4] > w_votes[16] ? 4 : (w_votes[16] > w_votes[8] ? 16 : 8);
+    sel_S.assign((size_t)count, S);
+    for (int i = 0; i < count; ++i) {
+      if (mats[i].m == 0 || mats[i].nnz == 0) continue;
+      const float *z = &scores[(size_t)i * SSS_N_CLASSES];
+      float best = -INFINITY;
+      for (int c = 0; c < SSS_N_CLASSES; ++c) {
+        int Wc = 0, Sc = 0;
+        (void)sss_class_params(c, &Wc, &Sc);
+        if (Wc == W && z[c] > best) { best = z[c]; sel_S[(size_t)i] = Sc; }
+      }
+    }
+  }
   const int WT = W * kWave;
   std::vector<MatCtx> ctx((size_t)count);
   std::vector<int64_t> bb((size_t)count + 1, 0), cb((size_t)count + 1, 0), sb((size_t)count + 1, 0);
@@ -1731,7 +1786,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
       return SSS_ERR_INVALID_VALUE;
     if (d.m > 0 && (!d.row_ptr || !d.y)) return SSS_ERR_INVALID_VALUE;
     if (d.nnz > 0 && (!d.col || !d.val || !d.x || misaligned(d.col) || misaligned(d.val))) return SSS_ERR_INVALID_VALUE;
-    const int Si = d.S ? d.S : S;
+    const int Si = !sel_S.empty() ? sel_S[(size_t)i] : (d.S ? d.S : S);
     if (Si < 1 || Si > kMaxS) return SSS_ERR_INVALID_VALUE;
     s_max = std::max(s_max, Si);
     const int64_t nb = (d.m > 0 && d.nnz > 0) ? (d.nnz + (int64_t)Si * WT - 1) / ((int64_t)Si * WT) : 0;
@@ -1759,6 +1814,8 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
 
   sss_plan p = new sss_plan_s();
   p->batch = true; p->dt = dt; p->W = W; p->S = S; p->B = B; p->batch_persistent = o.batch_persistent != 0;
+  p->mat_S.resize((size_t)count);
+  for (int i = 0; i < count; ++i) p->mat_S[(size_t)i] = ctx[(size_t)i].S;
   p->m = tot_m; p->n = tot_n; p->nnz = tot_nnz; p->n_tiles = tot_tiles; p->n_bunches = nb_all;
   auto fail = [&](hipError_t e) {
     g_last_hip = e;
@@ -1898,6 +1955,13 @@ int sss_batch_floor_probe(sss_plan p, void *out, int gather, void *stream) {
     case SSS_BF16: return launch_floor_batch_w<SSS_BF16>(p, out, gather, s);
     default: return SSS_ERR_UNSUPPORTED;
   }
+}
+
+int sss_batch_plan_schedule(sss_plan p, int count, int *W, int *S) {
+  if (!p || !p->batch || count != (int)p->mat_S.size()) return SSS_ERR_INVALID_VALUE;
+  if (W) *W = p->W;
+  if (S) std::copy(p->mat_S.begin(), p->mat_S.end(), S);
+  return SSS_OK;
 }
 
 int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t *n_bunches) {

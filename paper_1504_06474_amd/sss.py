@@ -64,6 +64,7 @@ def lib():
             raise SSSLibraryMissing(f"{LIB_PATH} is not built; run paper_1504_06474_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)
         P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        FP_ = ctypes.POINTER(ctypes.c_float)
         L.sss_csr_spmv_plan_create.argtypes = [I64, I64, I64, P, I, ctypes.POINTER(PlanOpts), P,
                                                ctypes.POINTER(P)]
         L.sss_csr_spmv_plan_workspace_size.argtypes = [I64, I64, I64, I, ctypes.POINTER(PlanOpts),
@@ -77,6 +78,8 @@ def lib():
         L.sss_batch_plan_create.argtypes = [I, ctypes.POINTER(CsrDesc), I, ctypes.POINTER(PlanOpts), P,
                                             ctypes.POINTER(P)]
         L.sss_batch_execute.argtypes = [P, P]
+        L.sss_batch_plan_schedule.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.sss_selector_scores.argtypes = [FP_, FP_]
         L.sss_batch_floor_probe.argtypes = [P, P, I, P]
         FP = ctypes.POINTER(ctypes.c_float)
         L.sss_class_params.argtypes = [I, ctypes.POINTER(I), ctypes.POINTER(I)]
@@ -116,7 +119,7 @@ def lib():
                   "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch", "sss_batch_floor_probe",
                   "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_csr_spmv_stage2_host", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
-                  "sss_selector_loaded", "sss_gather_probe"):
+                  "sss_selector_loaded", "sss_gather_probe", "sss_batch_plan_schedule", "sss_selector_scores"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -291,10 +294,12 @@ class BatchPlan:
     of one wavefront per thread-bunch."""
 
     def __init__(self, mats, dtype=torch.float64, W: int = 0, S: int = 0, B: int = 0, stream=None,
-                 persistent: bool = False):
+                 persistent: bool = False, mode: int = MODE_FIXED):
         L = lib()
         descs = self._describe(mats, dtype)
-        opts = PlanOpts(MODE_FIXED, W, S, B, 0, 0, 1 if persistent else 0)
+        if mode == MODE_SELECTOR and not L.sss_selector_loaded():
+            load_selector()
+        opts = PlanOpts(mode, W, S, B, 0, 0, 1 if persistent else 0)
         h = ctypes.c_void_p()
         _check(L.sss_batch_plan_create(len(mats), descs, self.dt, ctypes.byref(opts), _stream(stream),
                                        ctypes.byref(h)), "sss_batch_plan_create")
@@ -337,6 +342,14 @@ class BatchPlan:
 
     def info(self) -> dict:
         return Plan.info(self)
+
+    def schedule(self):
+        """(W, per-matrix S) of this plan (sss_batch_plan_schedule)."""
+        n = len(self._keep)
+        W = ctypes.c_int()
+        S = (ctypes.c_int * max(1, n))()
+        _check(lib().sss_batch_plan_schedule(self._h, n, ctypes.byref(W), S), "sss_batch_plan_schedule")
+        return W.value, list(S[:n])
 
     def execute(self, stream=None):
         _check(lib().sss_batch_execute(self._h, _stream(stream)), "sss_batch_execute")
@@ -452,6 +465,15 @@ def selector_set(params: np.ndarray, mean: np.ndarray, std: np.ndarray):
     FP = ctypes.POINTER(ctypes.c_float)
     _check(lib().sss_selector_set(p.ctypes.data_as(FP), mu.ctypes.data_as(FP), sd.ctypes.data_as(FP)),
            "sss_selector_set")
+
+
+def selector_scores(feats: np.ndarray) -> np.ndarray:
+    """The loaded selector's 12 class scores for one feature vector."""
+    f = np.ascontiguousarray(feats, dtype=np.float32)
+    z = np.zeros(N_CLASSES, dtype=np.float32)
+    FP = ctypes.POINTER(ctypes.c_float)
+    _check(lib().sss_selector_scores(f.ctypes.data_as(FP), z.ctypes.data_as(FP)), "sss_selector_scores")
+    return z
 
 
 def selector_predict(feats: np.ndarray) -> int:

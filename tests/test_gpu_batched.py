@@ -266,3 +266,87 @@ def test_batched_grid_schedule(torch_cuda):
         for (A, x), d in zip(mats, dev):
             assert_exact(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
     plan.close()
+
+
+def _selector_schedule(sss, dev, kind_dtype, W_given=0):
+    """The schedule the selector mode must produce, recomputed here from the
+    library's features (size features replaced by the batch's totals) and
+    class scores: W by nonzero-weighted vote of each matrix's best class
+    (unless given), then each matrix's best S with that W."""
+    classes = [sss.class_params(c) for c in range(12)]
+    scores, votes = [], {4: 0, 8: 0, 16: 0}
+    tot = [sum(d[0].numel() - 1 for d in dev), sum(d[5] for d in dev), sum(d[2].numel() for d in dev)]
+    for d in dev:
+        m, nnz = d[0].numel() - 1, d[2].numel()
+        if m == 0 or nnz == 0:
+            scores.append(None)
+            continue
+        f = sss.features(d[0], d[5], nnz, kind_dtype)
+        f[:3] = np.log2(np.asarray(tot, dtype=np.float64) + 1.0).astype(np.float32)
+        z = sss.selector_scores(f)
+        scores.append(z)
+        votes[classes[int(np.argmax(z))][0]] += nnz
+    W = W_given or (4 if votes[4] > votes[8] and votes[4] > votes[16] else (16 if votes[16] > votes[8] else 8))
+    S = []
+    for z in scores:
+        if z is None:
+            S.append(None)
+            continue
+        best = max((c for c in range(12) if classes[c][0] == W), key=lambda c: z[c])
+        S.append(classes[best][1])
+    return W, S
+
+
+@pytest.mark.parametrize("W_given", [0, 4])
+def test_batched_selector_schedule(torch_cuda, W_given):
+    """SELECTOR batch plans: each matrix's S is its best-scored class with the
+    batch's W (chosen by the selector's votes, or given); every y exact,
+    eager and replayed (integer-valued batch with edge shapes)."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    assert sss.load_selector()
+    mats = batch_set(True)
+    dev = to_dev(torch, mats, torch.float64)
+    plan = sss.BatchPlan(dev, mode=sss.MODE_SELECTOR, W=W_given)
+    W, S = plan.schedule()
+    W_want, S_want = _selector_schedule(sss, dev, torch.float64, W_given)
+    assert W == W_want
+    for s, s_want in zip(S, S_want):
+        if s_want is not None:
+            assert s == s_want
+    for launch in (plan.execute, plan.graph_launch):
+        for d in dev:
+            d[4].fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        for (A, x), d in zip(mats, dev):
+            assert_exact(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+    plan.close()
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_batched_selector_full_size_exact(torch_cuda, kind):
+    """The 512-matrix workload with the selector's per-matrix schedule (the
+    benchmark's selector-scheduled batch): every row of every matrix
+    bit-exact, eager and replayed."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    assert sss.load_selector()
+    tdt = torch.float64 if kind == "f64" else torch.float32
+    mats, refs = _full_set()
+    dev = to_dev(torch, mats, tdt)
+    plan = sss.BatchPlan(dev, dtype=tdt, mode=sss.MODE_SELECTOR)
+    W, S = plan.schedule()
+    note(f"  {kind} selector schedule W={W} S counts {np.bincount(S, minlength=9)[[1, 2, 4, 8]].tolist()}")
+    for launch in (plan.execute, plan.graph_launch):
+        for d in dev:
+            d[4].fill_(float("nan"))
+        torch.cuda.synchronize()
+        launch()
+        torch.cuda.synchronize()
+        for (A, _), d, ref in zip(mats, dev, refs):
+            assert_exact(d[4].double().cpu().numpy(), ref)
+    plan.close()
+    del dev
+    torch.cuda.empty_cache()
