@@ -43,22 +43,24 @@ def paper_bytes(m: int, nnz: int, val_size: int) -> int:
 
 
 def measured_traffic(W: int, S: int, B: int, bind_rows: bool):
-    """HBM-side bytes per stage-1 launch from the committed counter record,
-    or None when the device code (the kernel source file up to its host
-    side) or the launch shape differs from the one the counters were taken
-    on."""
+    """HBM-side bytes per stage-1 launch from the committed counter records
+    (one per launch shape), or None when the device code (the kernel source
+    file up to its host side) differs from the one the counters were taken
+    on, or no record has this launch shape."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     try:
-        rec = json.load(open(os.path.join(here, "profiles", "traffic.json")))["sss_stage1"]
+        doc = json.load(open(os.path.join(here, "profiles", "traffic.json")))
         src = open(os.path.join(here, "paper_1504_06474_amd", "csrc", "sss_spmv.hip"), "rb").read()
-    except (OSError, KeyError, ValueError):
+    except (OSError, ValueError):
         return None
     src = src[:src.index(b"struct sss_plan_s {")]  # the device code: every kernel precedes the host side
-    if (hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"] or (W, S, B) != (rec["W"], rec["S"], rec["B"])
-            or bool(rec.get("bind_rows", False)) != bool(bind_rows)):
+    if hashlib.sha256(src).hexdigest()[:16] != doc.get("source_sha256_16"):
         return None
-    return int(rec["fetch_kib_raw"] * rec["fetch_factor"] * 1024 + rec["write_kib_raw"] * rec["write_factor"] * 1024)
+    for rec in doc.get("sss_stage1", []):
+        if (W, S, B) == (rec["W"], rec["S"], rec["B"]) and bool(rec["bind_rows"]) == bool(bind_rows):
+            return int(rec["fetch_kib_raw"] * doc["fetch_factor"] * 1024 + rec["write_kib_raw"] * doc["write_factor"] * 1024)
+    return None
 
 
 def _cpu_model() -> str:
@@ -310,6 +312,13 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                     fl[name] = round(e0.elapsed_time(e1) / steps * 1e3, 2)
                 rec["floors"] = fl
                 del fo
+                # stage 1 alone, and the design-independent ceiling of this matrix's reads
+                rec["stage1_us"] = round(events_us(torch, lambda c: plan.stage1(*c), copies, steps, warmup), 2)
+                rec["gather_ceiling"] = gather_ceiling(torch, sss, copies, alg_bytes(A.m, A.n, A.nnz, vb, xb),
+                                                       max(5, steps // 2), 2)
+                rec["stage1_frac_of_probe_ceiling"] = round(rec["gather_ceiling"]["best_us"] / rec["stage1_us"], 3)
+                for c in copies:  # every copy's y back to a full product
+                    plan.execute(*c)
                 if kind == "f64":
                     rec["vs_rowwise"] = rowwise_comparison(torch, sss, copies, A.n, lambda c: plan.execute(*c))
                     log(f"[bench] precision f64 row-wise comparators: {rec['vs_rowwise']}")
@@ -408,20 +417,20 @@ def gather_ceiling(torch, sss, copies, alg: int, steps: int, warmup: int) -> dic
     val coalesced, x gathered), over a set of issue modes, depths and
     occupancies; the best reading is the design-independent ceiling."""
     xdt = copies[0][3].dtype
+    with_val = copies[0][2].dtype == xdt  # the probe streams val only when it shares x's type
     out_buf = torch.empty(1 << 20, dtype=xdt, device="cuda")
     res = {}
     for mode, U, wps in PROBE_CONFIGS:
         try:
-            sss.gather_probe(copies[0][1], copies[0][3], out_buf, copies[0][2] if copies[0][2].dtype == xdt else None,
-                             mode, U, wps)
+            sss.gather_probe(copies[0][1], copies[0][3], out_buf, copies[0][2] if with_val else None, mode, U, wps)
         except sss.SSSError:
             continue
-        us = events_us(torch, lambda c: sss.gather_probe(c[1], c[3], out_buf, c[2], mode, U, wps), copies,
-                       steps, warmup)
+        us = events_us(torch, lambda c: sss.gather_probe(c[1], c[3], out_buf, c[2] if with_val else None, mode, U, wps),
+                       copies, steps, warmup)
         res[f"{sss.GATHER_MODES[mode & 3]}{'_chunked' if mode & 4 else ''}_u{U}_w{wps}"] = round(us, 2)
     del out_buf
     best = min(res, key=res.get)
-    return {"probe_us": res, "best": best, "best_us": res[best],
+    return {"probe_us": res, "val_streamed": with_val, "best": best, "best_us": res[best],
             "best_alg_GBps": round(alg / (res[best] * 1e-6) / 1e9, 1),
             "best_frac_of_peak": round(alg / (res[best] * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4)}
 
@@ -827,6 +836,9 @@ def main():
     ap.add_argument("--B", type=int, default=0)
     ap.add_argument("--skip-extras", action="store_true",
                     help="time only the headline plan (no floor probes, no second plan variant): for profiling runs")
+    ap.add_argument("--extras", choices=["all", "ceiling", "none"], default="all",
+                    help="headline blocks beside the timed steps: all; only the floors and the gather ceiling "
+                         "(for counter runs); none (= --skip-extras)")
     ap.add_argument("--no-bind-rows", action="store_true",
                     help="search each thread-bunch's first row in every call instead of once at plan time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -842,6 +854,10 @@ def main():
                     help="the headline plan's (W, S): the library's grid autotuner (GRID plans), the learned "
                          "selector (SELECTOR plans) or the per-type default; --W/--S fix them instead")
     args = ap.parse_args()
+    if args.skip_extras:
+        args.extras = "none"
+    args.skip_extras = args.extras == "none"
+    comparators = args.extras == "all"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the multi-GPU path is not built (see the design notes on "
@@ -929,9 +945,16 @@ def main():
     torch.cuda.synchronize()
     s1 = np.array([ea[k].elapsed_time(eb[k]) for k in range(args.steps)])
     s2 = np.array([eb[k].elapsed_time(ec[k]) for k in range(args.steps)])
-    s1_ms = float(s1.mean())
+    s1_each_ms = float(s1.mean())
     s2_ms = float(s2.mean())
-    log(f"[bench] stage1 {s1_ms * 1e3:.2f} us, stage2 {s2_ms * 1e3:.2f} us")
+    # the roofline's kernel duration: stage 1 alone, K launches back to back
+    # between two events on the launch stream (an event pair around every
+    # launch adds a few microseconds per launch to what the kernel takes)
+    s1_ms = events_us(torch, lambda c: plan.stage1(*c), copies, args.steps, args.warmup) * 1e-3
+    for c in copies:  # every copy's y back to a full product
+        plan.execute(*c)
+    log(f"[bench] stage1 {s1_ms * 1e3:.2f} us back to back ({s1_each_ms * 1e3:.2f} us with events around each), "
+        f"stage2 {s2_ms * 1e3:.2f} us")
 
     # the distribution of whole steps: events around every step (the headline
     # above is the bracketed K-step time)
@@ -966,13 +989,13 @@ def main():
 
     # a plain device copy on the same device: the practical streaming rate
     copy_GBps = None
-    if not args.skip_extras:
+    if comparators:
         copy_GBps = round(2 * (1 << 30) / (device_copy_ms(torch, 10) * 1e-3) / 1e9, 1)
         log(f"[bench] device copy {copy_GBps} GB/s (read + write)")
 
     # the other plan variant (first rows searched in every call, or bound)
     ms_other = s1_other = float("nan")
-    if not args.skip_extras:
+    if comparators:
         other = PlanSet(sss, copies, m, n, nnz, not bind, dtype=torch.float64, W=info["W"], S=info["S"], B=args.B)
         ms_other = time_steps(torch, other, copies, args.steps, args.warmup)
         torch.cuda.synchronize()
@@ -991,7 +1014,7 @@ def main():
     # the per-type default plan (the paper's Table 3 values for its AMD GPU)
     # beside the headline plan, and the device's gather ceiling on this matrix
     default_rec = ceiling = None
-    if not args.skip_extras:
+    if comparators:
         dp = PlanSet(sss, copies, m, n, nnz, bind, dtype=torch.float64, B=args.B)
         dinfo = dp.info()
         default_rec = {"W": dinfo["W"], "S": dinfo["S"],
@@ -1003,26 +1026,27 @@ def main():
             plan.execute(*c)
         dp.close()
         log(f"[bench] default plan: {default_rec}")
+    if not args.skip_extras:
         ceiling = gather_ceiling(torch, sss, copies, alg_bytes(m, n, nnz, 8, 8), args.steps, args.warmup)
         ceiling["stage1_frac_of_ceiling"] = round(ceiling["best_us"] / (s1_ms * 1e3), 3)
         log(f"[bench] gather ceiling: {ceiling}")
 
     # the paper's comparison (Section 4.3) on this matrix: row-wise kernels
     comp_c2 = None
-    if not args.skip_extras:
+    if comparators:
         comp_c2 = rowwise_comparison(torch, sss, copies, n, lambda c: plan.execute(*c))
         log(f"[bench] row-wise comparators: {comp_c2}")
 
     # the paper's heterogeneous split (stage 2 on a host core) on this part
     host_s2 = None
-    if not args.skip_extras:
+    if comparators:
         host_s2 = host_stage2_block(torch, sss, plan, copies, A, x)
         host_s2["device_execute_us"] = round(ms_step * 1e3, 2)
         log(f"[bench] stage 2 on the host: {host_s2}")
 
     # the same matrix stored FP32 and BF16
     reduced = None
-    if not args.skip_extras:
+    if comparators:
         reduced = reduced_on_benchmark_matrix(torch, sss, A, x, ms_step, args.steps, args.warmup)
 
     # warm cache: the same copy every step
@@ -1073,8 +1097,9 @@ def main():
             "step_GBps": round(B / (ms_step * 1e-3) / 1e9, 1),
             "step_frac_of_peak": round(B / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4),
             "stage1_us": round(s1_ms * 1e3, 2),
+            "stage1_us_events_each": round(s1_each_ms * 1e3, 2),
             "stage2_us": round(s2_ms * 1e3, 2),
-            ("searching_plan" if bind else "bound_rows_plan"): None if args.skip_extras else {
+            ("searching_plan" if bind else "bound_rows_plan"): None if not comparators else {
                 "us_per_step": round(ms_other * 1e3, 2), "stage1_us": round(s1_other * 1e3, 2)},
             "per_step_us": per_step,
             "device_copy_GBps": copy_GBps,
