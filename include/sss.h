@@ -95,7 +95,11 @@ typedef struct {
                     Section 3.2 once, for every thread-bunch's first row, on
                     row_ptr (required); execute then reads those rows instead
                     of searching; the plan then serves only that row_ptr
-                    array (SSS_ERR_PLAN_MISMATCH for another) */
+                    array (SSS_ERR_PLAN_MISMATCH for another).  plan_create
+                    also lists the thread-bunches that hold a dirty tile
+                    (Section 3.2: an empty row r with row_ptr[r] > 0 lies in
+                    the tile), and stage 2 gives only those a re-arrangement
+                    wavefront instead of one per bunch */
   int batch_persistent; /* batch plans only.  0 (default): stage 1 launches one
                            wavefront per thread-bunch of every matrix.  Nonzero:
                            stage 1 is a persistent grid (as many workgroups as
@@ -149,7 +153,10 @@ int sss_csr_spmv_plan_workspace_size(int64_t m, int64_t n, int64_t nnz, sss_dtyp
  * checks each thread-bunch's stored first row against row_ptr's contents
  * (rp[r] <= b < rp[r + 1]) and searches again where it no longer holds, so
  * rewriting that array in place (same m and nnz) gives a correct y, at the
- * search's cost. */
+ * search's cost; a dirty tile in a bunch the plan did not list then marks
+ * the plan stale, and from that call on stage 2 also re-arranges the
+ * unlisted dirty bunches (one after another per 64 bunches: correct, slower;
+ * make a new plan for the new structure). */
 int sss_csr_spmv_execute(sss_plan p, const int32_t *row_ptr, const int32_t *col,
                          const void *val, const void *x, void *y, void *stream);
 
@@ -290,6 +297,15 @@ int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t 
  * SSS_ERR_INVALID_CSR. */
 int sss_validate_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr,
                      const int32_t *col, void *stream);
+
+/* The thread-bunches a bind_rows plan found, at plan time, to hold a dirty
+ * tile (Section 3.2's dirty condition on row_ptr), in increasing order: the
+ * first min(*n, cap) of them are copied to host_out (host, int32, may be NULL
+ * when cap = 0) and *n receives their number.  Stage 2 gives each listed
+ * bunch one re-arrangement wavefront.  A plan with no thread-bunch (m = 0 or
+ * nnz = 0) lists none.  SSS_ERR_INVALID_VALUE for a NULL plan or n, a batch
+ * plan, or a plan with bunches made without bind_rows. */
+int sss_plan_dirty_list(sss_plan p, int32_t *host_out, int64_t cap, int64_t *n);
 
 /* Debug: bytes needed by sss_plan_debug_dump for this plan. */
 int sss_plan_debug_size(sss_plan p, size_t *bytes);

@@ -297,7 +297,13 @@ struct MatCtx {
   double *sync_val;
   double *tail_val;      // per bunch: its last partial, when the bunch ends inside a row that is not
                          // its first row and continues into the next bunch (written only then)
-  const int32_t *bunch_row;  // per bunch: its first row, found at plan time (NULL: search)
+  const int32_t *bunch_row;  // per bunch: its first row, found at plan time (NULL: search); the top
+                             // bit is set on the bunches listed in dirty_list
+  const int32_t *dirty_list; // bound plans: the bunches whose tiles the plan found dirty (NULL: every
+                             // bunch gets a stage-2 wavefront)
+  int64_t n_fix;             // stage-2 re-arrangement wavefronts: entries of dirty_list, else n_bunches
+  int32_t *stale;            // bound plans: set (and never cleared) when stage 1 finds a dirty tile in a
+                             // bunch outside dirty_list (row_ptr rewritten in place since plan time)
   int32_t *dbg_start;    // debug plans only
   int32_t *dbg_dirty;
   uint32_t *dbg_heads;
@@ -444,7 +450,7 @@ __device__ __forceinline__ void products_in(const P *buf, int lane, P (&pr)[W]) 
 
 template <int DT, int W, bool DEBUG>
 __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, uint32_t *lds_wave, const int lane,
-                                             const int r0_known) {
+                                             const int r0_known, const bool listed = true) {
   using val_t = typename VT<DT>::val_t;
   using x_t = typename VT<DT>::x_t;
   using y_t = typename VT<DT>::y_t;
@@ -672,6 +678,9 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     a.sync_idx[tb] = r0;
     a.sync_val[tb] = sync_v;
     a.dirty_mask[tb] = dirty_bits;
+    // a bound plan re-arranges only the bunches it listed; a dirty tile
+    // anywhere else sends stage 2 to its fallback for every later call
+    if (dirty_bits && !listed) *a.stale = 1;
   }
 }
 
@@ -695,8 +704,14 @@ void sss_stage1(MatCtx a) {
   const int wid = threadIdx.x / kWave;
   const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
   if (tb >= a.n_bunches) return;
-  const int r0 = a.bunch_row ? a.bunch_row[tb] : -1;
-  stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane, r0);
+  int r0 = -1;
+  bool listed = true;
+  if (a.bunch_row) {
+    const int32_t br = a.bunch_row[tb];
+    r0 = br & 0x7fffffff;
+    listed = br < 0;
+  }
+  stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane, r0, listed);
 }
 
 // Plan time: the first row of every thread-bunch, the rightmost match of its
@@ -716,6 +731,19 @@ __global__ void sss_bunch_rows(const int32_t *__restrict__ rp, int32_t m, int64_
   for (int64_t tb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tb < n_bunches;
        tb += (int64_t)gridDim.x * blockDim.x)
     out[tb] = rightmost_row(rp, m, tb * SWT);
+}
+
+// Plan time, bound plans: set the top bit of bunch_row[tb] for every bunch
+// with a dirty tile.  A tile is dirty exactly when an empty row r with
+// row_ptr[r] = p > 0 lies in it (tile (p - 1) / WT, Section 3.2's dirty
+// condition), so its bunch is (p - 1) / SWT.
+__global__ void sss_mark_dirty_bunches(const int32_t *__restrict__ rp, int32_t m, int64_t SWT,
+                                       int32_t *__restrict__ bunch_row) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t p = rp[r];
+    if (p > 0 && p == rp[r + 1])
+      atomicOr(reinterpret_cast<unsigned int *>(bunch_row + (p - 1) / SWT), 0x80000000u);
+  }
 }
 
 // Plan time, batches: for global bunch g its matrix (the rightmost i with
@@ -1005,6 +1033,21 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
   __builtin_amdgcn_wave_barrier();
 }
 
+// (2b) a bound plan whose row_ptr was rewritten in place: the dirty bunches
+// of chunk0 .. chunk0+63 that its list lacks, one after another (the listed
+// ones have their own wavefronts).
+template <typename YT>
+__device__ __forceinline__ void fixup_unlisted(const MatCtx &a, const int64_t chunk0, YT *slots, const int lane) {
+  const int64_t tb = chunk0 + lane;
+  const bool todo = tb < a.n_bunches && a.bunch_row[tb] >= 0 && a.dirty_mask[tb] != 0;
+  uint64_t todo_bits = __ballot(todo);
+  while (todo_bits) {
+    const int l = __ffsll((unsigned long long)todo_bits) - 1;
+    todo_bits &= todo_bits - 1;
+    fixup_dirty<YT>(a, chunk0 + l, slots, lane);
+  }
+}
+
 // (3) rows before the first tile's start row are empty and covered by no
 // tile (all rows when nnz = 0): zero them, threads first..first+stride..
 template <typename YT>
@@ -1029,8 +1072,12 @@ __global__ __launch_bounds__(1024) void sss_fixup(MatCtx a) {
   YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
   const int64_t n_chunks = (a.n_bunches + kWave - 1) / kWave;
-  if (wave < n_chunks) fixup_carries<YT>(a, wave * kWave, lane, slots);
-  else if (wave < n_chunks + a.n_bunches) fixup_dirty<YT>(a, wave - n_chunks, slots, lane);
+  if (wave < n_chunks) {
+    fixup_carries<YT>(a, wave * kWave, lane, slots);
+    if (a.dirty_list && *a.stale) fixup_unlisted<YT>(a, wave * kWave, slots, lane);
+  } else if (wave < n_chunks + a.n_fix) {
+    fixup_dirty<YT>(a, a.dirty_list ? (int64_t)a.dirty_list[wave - n_chunks] : wave - n_chunks, slots, lane);
+  }
   fixup_leading<YT>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
@@ -1168,6 +1215,9 @@ struct sss_plan_s {
   double *sync_val = nullptr;
   double *tail_val = nullptr;
   int32_t *bunch_row = nullptr;  // plans made with bind_rows only
+  int32_t *dirty_list = nullptr; // bind_rows plans: the bunches with a dirty tile, found at plan time
+  int64_t n_listed = 0;
+  int32_t *stale = nullptr;      // bind_rows plans: one word, see MatCtx::stale
   int32_t *dbg_start = nullptr;
   int32_t *dbg_dirty = nullptr;
   uint32_t *dbg_heads = nullptr;
@@ -1191,7 +1241,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // entry per tile), every array 256-byte aligned.
 struct AuxLayout {
   int64_t n_tiles = 0, n_bunches = 0;
-  size_t dmask = 0, spec = 0, sidx = 0, sval = 0, tail = 0, brow = 0, dstart = 0, ddirty = 0, dheads = 0;
+  size_t dmask = 0, spec = 0, sidx = 0, sval = 0, tail = 0, brow = 0, dlist = 0, stale = 0, dstart = 0, ddirty = 0,
+         dheads = 0;
   size_t total = 0;
 };
 
@@ -1208,7 +1259,11 @@ AuxLayout aux_layout(int64_t nnz, int W, int S, bool bind, bool debug) {
   L.sidx = off; off = align256(off + sizeof(int32_t) * (nb + 1));
   L.sval = off; off = align256(off + sizeof(double) * (nb + 1));
   L.tail = off; off = align256(off + sizeof(double) * (nb + 1));
-  if (bind) { L.brow = off; off = align256(off + sizeof(int32_t) * (nb + 1)); }
+  if (bind) {
+    L.brow = off; off = align256(off + sizeof(int32_t) * (nb + 1));
+    L.dlist = off; off = align256(off + sizeof(int32_t) * (nb + 1));
+    L.stale = off; off = align256(off + sizeof(int32_t));
+  }
   if (debug) {
     L.dstart = off; off = align256(off + sizeof(int32_t) * (nt + 1));
     L.ddirty = off; off = align256(off + sizeof(int32_t) * (nt + 1));
@@ -1230,6 +1285,8 @@ void plan_bind_aux(sss_plan p, const AuxLayout &L, void *base_v) {
   p->sync_val = reinterpret_cast<double *>(base + L.sval);
   p->tail_val = reinterpret_cast<double *>(base + L.tail);
   p->bunch_row = p->bind_rows ? reinterpret_cast<int32_t *>(base + L.brow) : nullptr;
+  p->dirty_list = p->bind_rows ? reinterpret_cast<int32_t *>(base + L.dlist) : nullptr;
+  p->stale = p->bind_rows ? reinterpret_cast<int32_t *>(base + L.stale) : nullptr;
   p->dbg_start = p->debug ? reinterpret_cast<int32_t *>(base + L.dstart) : nullptr;
   p->dbg_dirty = p->debug ? reinterpret_cast<int32_t *>(base + L.ddirty) : nullptr;
   p->dbg_heads = p->debug ? reinterpret_cast<uint32_t *>(base + L.dheads) : nullptr;
@@ -1281,6 +1338,9 @@ MatCtx plan_ctx(sss_plan p, const int32_t *row_ptr, const int32_t *col, const vo
   a.dirty_mask = p->dirty_mask; a.speculator = p->speculator;
   a.sync_idx = p->sync_idx; a.sync_val = p->sync_val; a.tail_val = p->tail_val;
   a.bunch_row = p->bunch_row;
+  a.dirty_list = p->dirty_list;
+  a.n_fix = p->dirty_list ? p->n_listed : p->n_bunches;
+  a.stale = p->stale;
   a.dbg_start = p->dbg_start; a.dbg_dirty = p->dbg_dirty; a.dbg_heads = p->dbg_heads;
   return a;
 }
@@ -1315,9 +1375,9 @@ int launch_stage2(sss_plan p, const int32_t *row_ptr, void *y, hipStream_t strea
   const int WT = p->W * kWave;
   const MatCtx a2 = plan_ctx(p, row_ptr, nullptr, nullptr, nullptr, y);
   // one wavefront per 64 bunches (their carry runs), then one per thread-bunch
-  // (its dirty tiles)
+  // that can hold dirty tiles: every bunch, or a bound plan's listed ones
   const int wpb = fixup_waves_per_block(p->W, p->dt);
-  const int64_t waves2 = (p->n_bunches + kWave - 1) / kWave + p->n_bunches;
+  const int64_t waves2 = (p->n_bunches + kWave - 1) / kWave + a2.n_fix;
   const int64_t blocks2 = std::max<int64_t>(1, (waves2 + wpb - 1) / wpb);
   const size_t lds2 = (size_t)wpb * WT * y_size(p->dt);
   if (p->dt == SSS_F64)
@@ -1505,6 +1565,33 @@ int sss_csr_spmv_plan_workspace_size(int64_t m, int64_t n, int64_t nnz, sss_dtyp
   return SSS_OK;
 }
 
+namespace {
+
+// Bound plans: mark every bunch with a dirty tile on the device, then list
+// them on the host (bunch order) and copy the list to the plan; synchronises
+// `s`.
+int plan_list_dirty(sss_plan p, const int32_t *row_ptr, int64_t SWT, hipStream_t s) {
+  const size_t nb = (size_t)p->n_bunches;
+  const unsigned blocks = (unsigned)std::min<int64_t>((p->m + 255) / 256, 4096);
+  hipLaunchKernelGGL(sss_mark_dirty_bunches, dim3(blocks), dim3(256), 0, s, row_ptr, (int32_t)p->m, SWT,
+                     p->bunch_row);
+  SSS_HIP(hipGetLastError());
+  std::vector<int32_t> br(nb);
+  SSS_HIP(hipMemcpyAsync(br.data(), p->bunch_row, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SSS_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> list;
+  for (size_t tb = 0; tb < nb; ++tb)
+    if (br[tb] < 0) list.push_back((int32_t)tb);
+  p->n_listed = (int64_t)list.size();
+  if (!list.empty()) {
+    SSS_HIP(hipMemcpyAsync(p->dirty_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    SSS_HIP(hipStreamSynchronize(s));
+  }
+  return SSS_OK;
+}
+
+}  // namespace
+
 int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, sss_dtype dt,
                              const sss_plan_opts *opts, void *stream, sss_plan *out) {
   if (!out) return SSS_ERR_INVALID_VALUE;
@@ -1554,6 +1641,9 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
                        p->bunch_row);
     e = hipGetLastError();
     if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
+    // the bunches with a dirty tile (marked in bunch_row's top bit), listed
+    // in order so that stage 2 gives only them a wavefront
+    if (rc == SSS_OK) rc = plan_list_dirty(p, row_ptr, SWT, s);
   }
   if (rc == SSS_OK) {
     e = hipStreamSynchronize(s);
@@ -1565,6 +1655,15 @@ int sss_csr_spmv_plan_create(int64_t m, int64_t n, int64_t nnz, const int32_t *r
     return rc;
   }
   *out = p;
+  return SSS_OK;
+}
+
+int sss_plan_dirty_list(sss_plan p, int32_t *host_out, int64_t cap, int64_t *n) {
+  if (!p || !n || p->batch || cap < 0 || (cap > 0 && !host_out)) return SSS_ERR_INVALID_VALUE;
+  if (!p->bind_rows && p->n_bunches > 0) return SSS_ERR_INVALID_VALUE;  // (no bunches: nothing to list)
+  *n = p->n_listed;
+  const int64_t k = std::min(cap, p->n_listed);
+  if (k > 0) SSS_HIP(hipMemcpy(host_out, p->dirty_list, (size_t)k * sizeof(int32_t), hipMemcpyDeviceToHost));
   return SSS_OK;
 }
 

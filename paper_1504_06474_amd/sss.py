@@ -107,6 +107,7 @@ def lib():
         L.sss_validate_csr.argtypes = [I64, I64, I64, P, P, P]
         L.sss_plan_debug_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.sss_plan_debug_dump.argtypes = [P, P, ctypes.c_size_t]
+        L.sss_plan_dirty_list.argtypes = [P, P, I64, ctypes.POINTER(I64)]
         L.sss_status_string.argtypes = [I]
         L.sss_status_string.restype = ctypes.c_char_p
         L.sss_last_hip_error.restype = ctypes.c_char_p
@@ -116,7 +117,7 @@ def lib():
                   "sss_plan_destroy",
                   "sss_csr_spmv_stage1", "sss_csr_spmv_stage2",
                   "sss_plan_info", "sss_validate_csr", "sss_plan_debug_size", "sss_plan_debug_dump",
-                  "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch", "sss_batch_floor_probe",
+                  "sss_plan_dirty_list", "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch", "sss_batch_floor_probe",
                   "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_csr_spmv_stage2_host", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
                   "sss_selector_loaded", "sss_gather_probe", "sss_batch_plan_schedule", "sss_selector_scores"):
@@ -219,6 +220,15 @@ class Plan:
     def stage2(self, row_ptr, y, stream=None):
         """Checking prediction only (sss_csr_spmv_stage2)."""
         _check(lib().sss_csr_spmv_stage2(self._h, _ptr(row_ptr), _ptr(y), _stream(stream)), "sss_csr_spmv_stage2")
+
+    def dirty_list(self) -> np.ndarray:
+        """The thread-bunches a bind_rows plan listed at plan time as holding
+        a dirty tile (sss_plan_dirty_list)."""
+        n = ctypes.c_int64()
+        _check(lib().sss_plan_dirty_list(self._h, None, 0, ctypes.byref(n)), "sss_plan_dirty_list")
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        _check(lib().sss_plan_dirty_list(self._h, out.ctypes.data, n.value, ctypes.byref(n)), "sss_plan_dirty_list")
+        return out[:n.value].copy()
 
     def debug_dump(self) -> dict:
         L = lib()

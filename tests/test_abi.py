@@ -77,6 +77,8 @@ def test_host_side_argument_checks():
     assert L.sss_csr_spmv_stage1(None, None, None, None, None, None, None) == -1
     assert L.sss_csr_spmv_stage2(None, None, None, None) == -1
     assert L.sss_csr_spmv_stage2_host(None, None, None) == -1
+    n = ctypes.c_int64()
+    assert L.sss_plan_dirty_list(None, None, 0, ctypes.byref(n)) == -1
     assert L.sss_plan_destroy(None) == 0
 
 

@@ -390,6 +390,65 @@ def test_bound_plan_row_ptr_rewritten_in_place(torch_cuda, WS):
     assert_exact(y2, oracle.spmv(A2.row_ptr, A2.col, A2.val, x))
 
 
+def _dirty_bunches(row_ptr, W, S):
+    """Thread-bunches holding a dirty tile, by the oracle's definition of a
+    dirty tile (Section 3.2: an empty row inside the tile's row range)."""
+    return np.unique(np.nonzero(sp.dirty_tiles_vec(row_ptr, 64, W))[0] // S).astype(np.int32)
+
+
+@pytest.mark.parametrize("name", sorted(EDGE) + ["config1", "no_empty_rows"])
+@pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
+def test_bound_plan_dirty_list(torch_cuda, name, WS):
+    """A bound plan lists at plan time exactly the thread-bunches that the
+    oracle's dirty-tile definition marks, stage 1's dirty flags fall in the
+    same bunches, and y is exact (stage 2 re-arranges only listed bunches)."""
+    if name == "config1":
+        A, x = csrgen.config1(int_valued=True)
+    elif name == "no_empty_rows":
+        A, x = csr_from_lengths([27] * 5000, 5000, seed=27)
+    else:
+        lengths, n = EDGE[name]
+        A, x = csr_from_lengths(lengths, n, seed=len(lengths))
+    note(f"  {name} m={A.m} nnz={A.nnz} W,S={WS}")
+    y, p = run_plan(torch_cuda, A, x, W=WS[0], S=WS[1], debug=True, bind_rows=True)
+    listed = p.dirty_list()
+    assert np.array_equal(listed, _dirty_bunches(A.row_ptr, *WS))
+    d = p.debug_dump()
+    assert np.array_equal(np.unique(np.nonzero(d["tile_dirty"])[0] // WS[1]), listed)
+    assert_exact(y, oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+@pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
+def test_bound_plan_without_dirty_bunches_rewritten_with_empty_rows(torch_cuda, WS):
+    """A bound plan made for a matrix with no empty row lists no bunch.  Its
+    row_ptr rewritten in place with empty rows (same m and nnz) makes tiles
+    dirty outside the list: stage 1 marks the plan stale and stage 2 then
+    re-arranges those bunches itself, so y stays exact call after call, and
+    again once the first structure is written back."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    lens = np.full(4000, 9, dtype=np.int64)
+    A, x = csr_from_lengths(lens, 600, seed=5)
+    pick = csrgen.rng_for(6).choice(4000, size=400, replace=False)
+    lens2 = lens.copy()
+    lens2[pick[:200]] = 0
+    lens2[pick[200:]] += 9
+    rp2 = np.zeros(A.m + 1, dtype=np.int64)
+    np.cumsum(lens2, out=rp2[1:])
+    A2 = csrgen.CSR(A.m, A.n, rp2.astype(np.int32), A.col, A.val, "rows_emptied")
+    rp, col, v, xx = to_dev(A, x)
+    plan = sss.Plan(A.m, A.n, A.nnz, W=WS[0], S=WS[1], bind_rows=True, row_ptr=rp)
+    assert plan.dirty_list().size == 0
+    want1 = oracle.spmv(A.row_ptr, A.col, A.val, x)
+    want2 = oracle.spmv(A2.row_ptr, A2.col, A2.val, x)
+    assert_exact(plan.execute(rp, col, v, xx).cpu().numpy(), want1)
+    rp.copy_(torch.from_numpy(A2.row_ptr).to("cuda"))
+    for _ in range(2):
+        assert_exact(plan.execute(rp, col, v, xx).cpu().numpy(), want2)
+    rp.copy_(torch.from_numpy(A.row_ptr).to("cuda"))
+    assert_exact(plan.execute(rp, col, v, xx).cpu().numpy(), want1)
+
+
 def test_plan_workspace(torch_cuda):
     """A plan in a caller's workspace (as the binding makes them, from
     PyTorch's allocator) and a plan with its own allocation give bitwise the
