@@ -450,7 +450,7 @@ __device__ __forceinline__ void products_in(const P *buf, int lane, P (&pr)[W]) 
 
 template <int DT, int W, bool DEBUG>
 __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, uint32_t *lds_wave, const int lane,
-                                             const int r0_known, const bool listed = true) {
+                                             const int32_t brow) {
   using val_t = typename VT<DT>::val_t;
   using x_t = typename VT<DT>::x_t;
   using y_t = typename VT<DT>::y_t;
@@ -481,8 +481,13 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
   // ---- tile boundary search (rightmost match) for the bunch's first row,
   // unless the plan found it once for all calls; such a row is checked in the
   // row pass below
-  int r0 = r0_known >= 0 ? r0_known : wave_rightmost(rp, m, b0, lane);
-  bool verify = r0_known >= 0;
+  // brow: -1 = search for the first row; else the first row found at plan
+  // time, top bit set when the plan listed this bunch as dirty (decoded
+  // here, after tile 0's loads are issued, so nothing waits for it earlier)
+  const bool known = brow != -1;
+  const bool listed = brow < 0;
+  int r0 = known ? (brow & 0x7fffffff) : wave_rightmost(rp, m, b0, lane);
+  bool verify = known;
 
   // ---- x gathers of tile 0: they need only the columns, so they go out
   // before the row pass and travel with its loads
@@ -680,7 +685,7 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     a.dirty_mask[tb] = dirty_bits;
     // a bound plan re-arranges only the bunches it listed; a dirty tile
     // anywhere else sends stage 2 to its fallback for every later call
-    if (dirty_bits && !listed) *a.stale = 1;
+    if (dirty_bits && !listed && a.stale) *a.stale = 1;
   }
 }
 
@@ -704,14 +709,8 @@ void sss_stage1(MatCtx a) {
   const int wid = threadIdx.x / kWave;
   const int64_t tb = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid;
   if (tb >= a.n_bunches) return;
-  int r0 = -1;
-  bool listed = true;
-  if (a.bunch_row) {
-    const int32_t br = a.bunch_row[tb];
-    r0 = br & 0x7fffffff;
-    listed = br < 0;
-  }
-  stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane, r0, listed);
+  const int32_t brow = a.bunch_row ? a.bunch_row[tb] : -1;
+  stage1_bunch<DT, W, DEBUG>(a, tb, lds_words + wid * stage1_lds_words(W, a.S), lane, brow);
 }
 
 // Plan time: the first row of every thread-bunch, the rightmost match of its
