@@ -732,16 +732,16 @@ __global__ void sss_bunch_rows(const int32_t *__restrict__ rp, int32_t m, int64_
     out[tb] = rightmost_row(rp, m, tb * SWT);
 }
 
-// Plan time, bound plans: set the top bit of bunch_row[tb] for every bunch
-// with a dirty tile.  A tile is dirty exactly when an empty row r with
+// Plan time: mark every bunch with a dirty tile by OR-ing `bit` into
+// words[bunch * stride].  A tile is dirty exactly when an empty row r with
 // row_ptr[r] = p > 0 lies in it (tile (p - 1) / WT, Section 3.2's dirty
-// condition), so its bunch is (p - 1) / SWT.
+// condition), so its bunch is (p - 1) / SWT.  Single plans mark the top bit
+// of bunch_row, batch plans the last word of each bunch's bunch_info entry.
 __global__ void sss_mark_dirty_bunches(const int32_t *__restrict__ rp, int32_t m, int64_t SWT,
-                                       int32_t *__restrict__ bunch_row) {
+                                       uint32_t *__restrict__ words, int stride, uint32_t bit) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
     const int32_t p = rp[r];
-    if (p > 0 && p == rp[r + 1])
-      atomicOr(reinterpret_cast<unsigned int *>(bunch_row + (p - 1) / SWT), 0x80000000u);
+    if (p > 0 && p == rp[r + 1]) atomicOr(words + (p - 1) / SWT * stride, bit);
   }
 }
 
@@ -823,8 +823,11 @@ struct BatchArgs {
   int32_t S_max;
   int64_t total_bunches;
   int64_t total_chunks;
-  int64_t total_waves;        // stage-2 work items: total_chunks + total_bunches + count
-  const int4 *bunch_info;     // per global bunch: <matrix, first row, bunch within the matrix, 0>
+  int64_t total_waves;        // stage-2 work items: total_chunks + n_fix + count
+  int64_t n_fix;              // stage-2 re-arrangement items: the listed bunches
+  const int32_t *dirty_list;  // the global bunches found at plan time to hold a dirty tile
+  int32_t *stale;             // set when stage 1 finds a dirty tile in an unlisted bunch
+  const int4 *bunch_info;     // per global bunch: <matrix, first row, bunch within the matrix, listed>
 };
 
 // gfx950 (one partition) hands consecutive workgroups to its 8 XCDs in turn,
@@ -852,7 +855,7 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
   if (g >= b.total_bunches) return;
   const int4 bi = b.bunch_info[g];
   const MatCtx a = b.mats[bi.x];
-  stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.y);
+  stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.w ? (int32_t)((uint32_t)bi.y | 0x80000000u) : bi.y);
 }
 
 // The same work as a persistent grid (batch_persistent plans): as many
@@ -873,7 +876,7 @@ __global__ __launch_bounds__(256) void sss_stage1_batch_persistent(BatchArgs b) 
   for (int64_t g = b.total_bunches * k / G + (int64_t)(blockIdx.x / G) * wpb + wid; g < hi; g += stride) {
     const int4 bi = b.bunch_info[g];
     const MatCtx a = b.mats[bi.x];
-    stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.y);
+    stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.w ? (int32_t)((uint32_t)bi.y | 0x80000000u) : bi.y);
   }
 }
 
@@ -1036,9 +1039,13 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
 // of chunk0 .. chunk0+63 that its list lacks, one after another (the listed
 // ones have their own wavefronts).
 template <typename YT>
-__device__ __forceinline__ void fixup_unlisted(const MatCtx &a, const int64_t chunk0, YT *slots, const int lane) {
+__device__ __forceinline__ void fixup_unlisted(const MatCtx &a, const int64_t chunk0, YT *slots, const int lane,
+                                               const int4 *binfo = nullptr) {
+  // listed: the top bit of bunch_row (single plans), or the last word of the
+  // bunch's entry in binfo (a batch's entries of this matrix)
   const int64_t tb = chunk0 + lane;
-  const bool todo = tb < a.n_bunches && a.bunch_row[tb] >= 0 && a.dirty_mask[tb] != 0;
+  bool todo = false;
+  if (tb < a.n_bunches && a.dirty_mask[tb] != 0) todo = binfo ? binfo[tb].w == 0 : a.bunch_row[tb] >= 0;
   uint64_t todo_bits = __ballot(todo);
   while (todo_bits) {
     const int l = __ffsll((unsigned long long)todo_bits) - 1;
@@ -1094,16 +1101,18 @@ __global__ __launch_bounds__(1024) void sss_fixup_batch(BatchArgs b) {
     if (w < b.total_chunks) {
       const int i = (int)wave_rightmost(b.chunk_base, (int64_t)b.count, w, lane);
       const MatCtx a = b.mats[i];
-      fixup_carries<YT>(a, (w - b.chunk_base[i]) * kWave, lane,
-                        reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave);
-    } else if (w < b.total_chunks + b.total_bunches) {
-      const int64_t g = w - b.total_chunks;
+      YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
+      const int64_t chunk0 = (w - b.chunk_base[i]) * kWave;
+      fixup_carries<YT>(a, chunk0, lane, slots);
+      if (*b.stale) fixup_unlisted<YT>(a, chunk0, slots, lane, b.bunch_info + b.bunch_base[i]);
+    } else if (w < b.total_chunks + b.n_fix) {
+      const int64_t g = b.dirty_list[w - b.total_chunks];
       const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane);
       const MatCtx a = b.mats[i];
       YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
       fixup_dirty<YT>(a, g - b.bunch_base[i], slots, lane);
     } else {
-      const MatCtx a = b.mats[w - b.total_chunks - b.total_bunches];
+      const MatCtx a = b.mats[w - b.total_chunks - b.n_fix];
       fixup_leading<YT>(a, lane, kWave);
     }
   }
@@ -1573,7 +1582,7 @@ int plan_list_dirty(sss_plan p, const int32_t *row_ptr, int64_t SWT, hipStream_t
   const size_t nb = (size_t)p->n_bunches;
   const unsigned blocks = (unsigned)std::min<int64_t>((p->m + 255) / 256, 4096);
   hipLaunchKernelGGL(sss_mark_dirty_bunches, dim3(blocks), dim3(256), 0, s, row_ptr, (int32_t)p->m, SWT,
-                     p->bunch_row);
+                     reinterpret_cast<uint32_t *>(p->bunch_row), 1, 0x80000000u);
   SSS_HIP(hipGetLastError());
   std::vector<int32_t> br(nb);
   SSS_HIP(hipMemcpyAsync(br.data(), p->bunch_row, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1909,6 +1918,8 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   const size_t o_sv = off; off = align256(off + sizeof(double) * (size_t)(nb_all + 1));
   const size_t o_tv = off; off = align256(off + sizeof(double) * (size_t)(nb_all + 1));
   const size_t o_bi = off; off = align256(off + sizeof(int4) * (size_t)(nb_all + 1));
+  const size_t o_dl = off; off = align256(off + sizeof(int32_t) * (size_t)(nb_all + 1));
+  const size_t o_st = off; off = align256(off + sizeof(int32_t));
 
   sss_plan p = new sss_plan_s();
   p->batch = true; p->dt = dt; p->W = W; p->S = S; p->B = B; p->batch_persistent = o.batch_persistent != 0;
@@ -1937,6 +1948,7 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
     c.sync_idx = reinterpret_cast<int32_t *>(base + o_si) + bb[(size_t)i];
     c.sync_val = reinterpret_cast<double *>(base + o_sv) + bb[(size_t)i];
     c.tail_val = reinterpret_cast<double *>(base + o_tv) + bb[(size_t)i];
+    c.stale = reinterpret_cast<int32_t *>(base + o_st);
   }
   // host arrays stay alive until the stream synchronisation below
   if (count > 0)
@@ -1954,7 +1966,8 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
   ba.S_max = s_max;
   ba.total_bunches = nb_all;
   ba.total_chunks = cb[(size_t)count];
-  ba.total_waves = ba.total_chunks + nb_all + count;
+  ba.dirty_list = reinterpret_cast<const int32_t *>(base + o_dl);
+  ba.stale = reinterpret_cast<int32_t *>(base + o_st);
   // every global bunch's matrix, first row and index within the matrix, once
   // for all calls (the descriptors, and so the row pointers, are bound to the plan)
   int4 *binfo = reinterpret_cast<int4 *>(base + o_bi);
@@ -1965,9 +1978,34 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
                        binfo);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
+    // the bunches with a dirty tile, marked in their bunch_info entries
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
+      const MatCtx &c = ctx[(size_t)i];
+      if (c.n_bunches == 0) continue;
+      const unsigned mb = (unsigned)std::min<int64_t>(((int64_t)c.m + 255) / 256, 4096);
+      hipLaunchKernelGGL(sss_mark_dirty_bunches, dim3(mb), dim3(256), 0, s, c.row_ptr, c.m, (int64_t)c.S * WT,
+                         reinterpret_cast<uint32_t *>(binfo + bb[(size_t)i]) + 3, 4, 1u);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return fail(e);
   }
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(e);
+  // list them in order, so that stage 2 gives only them a work item
+  std::vector<int32_t> dlist;
+  if (nb_all > 0) {
+    std::vector<int4> bi_host((size_t)nb_all);
+    e = hipMemcpy(bi_host.data(), binfo, sizeof(int4) * (size_t)nb_all, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(e);
+    for (int64_t g = 0; g < nb_all; ++g)
+      if (bi_host[(size_t)g].w) dlist.push_back((int32_t)g);
+    if (!dlist.empty()) {
+      e = hipMemcpy(base + o_dl, dlist.data(), sizeof(int32_t) * dlist.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return fail(e);
+    }
+  }
+  ba.n_fix = (int64_t)dlist.size();
+  ba.total_waves = ba.total_chunks + ba.n_fix + count;
   // stage 2's persistent grid: as many workgroups as stay resident on the device
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);

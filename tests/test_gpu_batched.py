@@ -61,6 +61,44 @@ def test_batched_integer_exact(torch_cuda, WS, persistent):
 
 
 @pytest.mark.parametrize("persistent", [False, True])
+def test_batched_row_ptr_rewritten_in_place(torch_cuda, persistent):
+    """A batch plan lists its dirty bunches at plan time.  One matrix's
+    row_ptr rewritten in place with empty rows (same m and nnz) makes tiles
+    dirty outside the list: stage 1 marks the plan stale and stage 2's carry
+    items then re-arrange those bunches too, so every y stays exact, call
+    after call, and again once the first structure is written back."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    lens = np.full(4000, 9, dtype=np.int64)
+    A0, x0 = csr_from_lengths(lens, 600, seed=61, int_valued=True)
+    mats = [(A0, x0), csr_from_lengths([3, 1, 0, 0, 2] * 500, 900, seed=62, int_valued=True),
+            csr_from_lengths([7] * 3000, 500, seed=63, int_valued=True)]
+    pick = csrgen.rng_for(64).choice(4000, size=400, replace=False)
+    lens2 = lens.copy()
+    lens2[pick[:200]] = 0
+    lens2[pick[200:]] += 9
+    rp2 = np.zeros(A0.m + 1, dtype=np.int64)
+    np.cumsum(lens2, out=rp2[1:])
+    A0b = csrgen.CSR(A0.m, A0.n, rp2.astype(np.int32), A0.col, A0.val, "rows_emptied")
+    dev = to_dev(torch, mats, torch.float64)
+    plan = sss.BatchPlan(dev, W=8, S=2, persistent=persistent)
+
+    def check(first):
+        plan.execute()
+        torch.cuda.synchronize()
+        for k, ((A, x), d) in enumerate(zip(mats, dev)):
+            A = first if k == 0 else A
+            assert_exact(d[4].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+    check(A0)
+    dev[0][0].copy_(torch.from_numpy(A0b.row_ptr).cuda())
+    check(A0b)
+    check(A0b)
+    dev[0][0].copy_(torch.from_numpy(A0.row_ptr).cuda())
+    check(A0)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
 @pytest.mark.parametrize("bunches", [1, 3, 17, 33])
 def test_batched_small_grids(torch_cuda, bunches, persistent):
     """Batches of 1, 3, 17 and 33 thread-bunches (W = 8, S = 5, B = 2): stage
