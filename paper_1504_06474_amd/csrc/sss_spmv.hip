@@ -208,7 +208,18 @@ __device__ __forceinline__ I wave_rightmost(const T *__restrict__ rp, I m, T b, 
 // (into rows 2 and 3).  Lanes whose source is out of range read 0, the
 // identity of both scans below.
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
-constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+
+// lane l reads lane l + 1; the last lane keeps `last`
+__device__ __forceinline__ int wave_next(int v, int last) {
+  return __builtin_amdgcn_update_dpp(last, v, kWaveShl1, 0xf, 0xf, false);
+}
+// lane l reads lane l - 1; lane 0 keeps `first`
+__device__ __forceinline__ int wave_prev(int v, int first) {
+  return __builtin_amdgcn_update_dpp(first, v, kWaveShr1, 0xf, 0xf, false);
+}
+// v of lane `l`, for a lane index the same in every lane
+__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ int dpp_i(int v) {
@@ -503,18 +514,19 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
   const int my_b = (int)imin64(tb * SWT + (int64_t)min(lane, S) * WT, nnz);
   int my_count = 0;  // lane t <= S: rows r >= r0 with rp[r] <= b_t
   int my_rp = 0;     // lane t <= S: rp of the last such row (the tile's start row)
-  for (int rbase = r0;; rbase += kWave) {
+  for (int rbase = __builtin_amdgcn_readfirstlane(r0);; rbase += kWave) {
     const int r = rbase + lane;
     const int p = (r <= m) ? rp[r] : INT_MAX;
-    const int q = (r < m) ? rp[r + 1] : INT_MAX;
+    // q = rp[r + 1]: the next lane's p, and one uniform load for the last lane
+    const int q = wave_next(p, (rbase + kWave - 1 < m) ? rp[rbase + kWave] : INT_MAX);
     if (verify) {
       // a row found at plan time is the rightmost match of b0 exactly when
       // rp[r0] <= b0 < rp[r0 + 1]; if row_ptr no longer says so, search
       // (the pass has accumulated nothing yet)
       verify = false;
-      const int p0 = __shfl(p, 0, kWave), q0 = __shfl(q, 0, kWave);
+      const int p0 = lane_value(p, 0), q0 = lane_value(q, 0);
       if (!(p0 <= b0 && b0 < q0)) {
-        r0 = wave_rightmost(rp, m, b0, lane);
+        r0 = __builtin_amdgcn_readfirstlane(wave_rightmost(rp, m, b0, lane));
         rbase = r0 - kWave;
         continue;
       }
@@ -529,15 +541,15 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     for (int t = 0; t <= S; ++t) {
       // rows with rp <= b_t are a prefix of the chunk; the last of them
       // (so far) is the start row of tile t
-      const int bt = __shfl(my_b, t, kWave);
+      const int bt = lane_value(my_b, t);
       const int c = __popcll(__ballot(p <= bt));
-      const int p_last_in = __shfl(p, c > 0 ? c - 1 : 0, kWave);
+      const int p_last_in = lane_value(p, c > 0 ? c - 1 : 0);
       if (lane == t) {
         my_count += c;
         if (c > 0) my_rp = p_last_in;
       }
     }
-    const int p_last = __shfl(p, kWave - 1, kWave);
+    const int p_last = lane_value(p, kWave - 1);
     if (!(p_last <= bS && rbase + (kWave - 1) < m)) break;
   }
   __builtin_amdgcn_wave_barrier();
@@ -551,9 +563,9 @@ __device__ __forceinline__ void stage1_bunch(const MatCtx &a, const int64_t tb, 
     if (b64 >= nnz) break;
     const int b = (int)b64;
     const int e = (int)imin64(b64 + WT, nnz);
-    const int start = __shfl(my_start, t, kWave);
-    const int stop = __shfl(my_start, t + 1, kWave);
-    const int rp_stop = __shfl(my_rp, t + 1, kWave);
+    const int start = lane_value(my_start, t);
+    const int stop = lane_value(my_start, t + 1);
+    const int rp_stop = lane_value(my_rp, t + 1);
     const bool ends_mid = (stop < m) && (rp_stop < e);
     const bool dirty = (dirty_bits >> t) & 1u;
     const int64_t tile = tb * S + t;
@@ -921,8 +933,8 @@ __device__ __forceinline__ void fixup_dirty(const MatCtx &a, const int64_t tb, Y
     ent_lane = make_int2(s.x, s.y);
   }
   for (int ent = 0; ent < n_dirty; ++ent) {
-    const int start = __shfl(ent_lane.x, ent, kWave);
-    const int stop = __shfl(ent_lane.y, ent, kWave);
+    const int start = lane_value(ent_lane.x, ent);
+    const int stop = lane_value(ent_lane.y, ent);
     const int n_slots = min(stop - start - 1, WT - 1);
     // the first chunk's row bounds and the partials do not depend on each
     // other: issue both before waiting
@@ -996,8 +1008,7 @@ __device__ __forceinline__ void fixup_carries(const MatCtx &a, const int64_t chu
   // one wavefront owns `lds` and its LDS operations run in order
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  int prev = __shfl(idx, (lane + kWave - 1) & (kWave - 1), kWave);
-  if (lane == 0) prev = before_chunk;
+  const int prev = wave_prev(idx, before_chunk);
   const bool head = valid && (tb == 0 || prev != idx);
   const bool is_long = head && (tb + kShortRun < nb) && (s_idx[lane + kShortRun] == idx);
   if (head && !is_long) {
