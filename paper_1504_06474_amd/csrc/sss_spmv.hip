@@ -221,6 +221,21 @@ __device__ __forceinline__ int wave_prev(int v, int first) {
 // v of lane `l`, for a lane index the same in every lane
 __device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// *p for an address the same in every lane, of data no kernel of the launch
+// writes (plan arrays written before it): read through the scalar unit into
+// scalar registers instead of once per lane into vector registers
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  uint32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = ((cword *)p)[i];
+  T v;
+  __builtin_memcpy(&v, w, sizeof(T));
+  return v;
+}
+
 template <int CTRL, int ROWS>
 __device__ __forceinline__ int dpp_i(int v) {
   return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, true);
@@ -842,6 +857,21 @@ struct BatchArgs {
   const int4 *bunch_info;     // per global bunch: <matrix, first row, bunch within the matrix, listed>
 };
 
+// A global bunch's plan entry and its matrix's context, read once per
+// wavefront: through the scalar unit into scalar registers, except for W = 16,
+// whose register budget the scalar copy of the context pushes past the next
+// occupancy step (g < 2^31: the grid is limited to that many wavefronts).
+template <int W>
+__device__ __forceinline__ void batch_entry(const BatchArgs &b, int64_t g, int4 &bi, MatCtx &a) {
+  if constexpr (W == 16) {
+    bi = b.bunch_info[g];
+    a = b.mats[bi.x];
+  } else {
+    bi = uniform_load(b.bunch_info + __builtin_amdgcn_readfirstlane((int)g));
+    a = uniform_load(b.mats + bi.x);
+  }
+}
+
 // gfx950 (one partition) hands consecutive workgroups to its 8 XCDs in turn,
 // workgroup b to XCD b mod 8, and every XCD has its own L2.
 constexpr int kXcds = 8;
@@ -865,8 +895,9 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
   const int64_t wg = (int64_t)(blockIdx.x % G) * per + blockIdx.x / G;
   const int64_t g = wg * (blockDim.x / kWave) + wid;
   if (g >= b.total_bunches) return;
-  const int4 bi = b.bunch_info[g];
-  const MatCtx a = b.mats[bi.x];
+  int4 bi;
+  MatCtx a;
+  batch_entry<W>(b, g, bi, a);
   stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.w ? (int32_t)((uint32_t)bi.y | 0x80000000u) : bi.y);
 }
 
@@ -886,8 +917,9 @@ __global__ __launch_bounds__(256) void sss_stage1_batch_persistent(BatchArgs b) 
   const int64_t stride = (int64_t)((gridDim.x - k + G - 1) / G) * wpb;  // waves of the workgroups b mod G = k
   const int64_t hi = b.total_bunches * (k + 1) / G;
   for (int64_t g = b.total_bunches * k / G + (int64_t)(blockIdx.x / G) * wpb + wid; g < hi; g += stride) {
-    const int4 bi = b.bunch_info[g];
-    const MatCtx a = b.mats[bi.x];
+    int4 bi;
+    MatCtx a;
+    batch_entry<W>(b, g, bi, a);
     stage1_bunch<DT, W, false>(a, bi.z, lds_wave, lane, bi.w ? (int32_t)((uint32_t)bi.y | 0x80000000u) : bi.y);
   }
 }
@@ -905,8 +937,9 @@ __global__ __launch_bounds__(256) void sss_floor_batch(BatchArgs b, typename VT<
   const int64_t wg = (int64_t)(blockIdx.x % G) * per + blockIdx.x / G;
   const int64_t g = wg * (blockDim.x / kWave) + wid;
   if (g >= b.total_bunches) return;
-  const int4 bi = b.bunch_info[g];
-  const MatCtx a = b.mats[bi.x];
+  int4 bi;
+  MatCtx a;
+  batch_entry<W>(b, g, bi, a);
   out[g * kWave + lane] = (typename VT<DT>::y_t)floor_bunch<DT, W, GATHER>(a, bi.z, lane);
 }
 
@@ -1110,20 +1143,20 @@ __global__ __launch_bounds__(1024) void sss_fixup_batch(BatchArgs b) {
   const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wid; w < b.total_waves; w += n_waves) {
     if (w < b.total_chunks) {
-      const int i = (int)wave_rightmost(b.chunk_base, (int64_t)b.count, w, lane);
-      const MatCtx a = b.mats[i];
+      const int i = __builtin_amdgcn_readfirstlane((int)wave_rightmost(b.chunk_base, (int64_t)b.count, w, lane));
+      const MatCtx a = uniform_load(b.mats + i);
       YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
-      const int64_t chunk0 = (w - b.chunk_base[i]) * kWave;
+      const int64_t chunk0 = (w - uniform_load(b.chunk_base + i)) * kWave;
       fixup_carries<YT>(a, chunk0, lane, slots);
-      if (*b.stale) fixup_unlisted<YT>(a, chunk0, slots, lane, b.bunch_info + b.bunch_base[i]);
+      if (*b.stale) fixup_unlisted<YT>(a, chunk0, slots, lane, b.bunch_info + uniform_load(b.bunch_base + i));
     } else if (w < b.total_chunks + b.n_fix) {
       const int64_t g = b.dirty_list[w - b.total_chunks];
-      const int i = (int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane);
-      const MatCtx a = b.mats[i];
+      const int i = __builtin_amdgcn_readfirstlane((int)wave_rightmost(b.bunch_base, (int64_t)b.count, g, lane));
+      const MatCtx a = uniform_load(b.mats + i);
       YT *slots = reinterpret_cast<YT *>(lds_raw) + (size_t)wid * a.W * kWave;
-      fixup_dirty<YT>(a, g - b.bunch_base[i], slots, lane);
+      fixup_dirty<YT>(a, g - uniform_load(b.bunch_base + i), slots, lane);
     } else {
-      const MatCtx a = b.mats[w - b.total_chunks - b.n_fix];
+      const MatCtx a = uniform_load(b.mats + __builtin_amdgcn_readfirstlane((int)(w - b.total_chunks - b.n_fix)));
       fixup_leading<YT>(a, lane, kWave);
     }
   }
