@@ -317,6 +317,8 @@ def precision_block(torch, sss, steps: int, warmup: int) -> dict:
                 rec["gather_ceiling"] = gather_ceiling(torch, sss, copies, alg_bytes(A.m, A.n, A.nnz, vb, xb),
                                                        max(5, steps // 2), 2)
                 rec["stage1_frac_of_probe_ceiling"] = round(rec["gather_ceiling"]["best_us"] / rec["stage1_us"], 3)
+                rec["stage1_frac_of_probe_ceiling_with_rows"] = round(
+                    rec["gather_ceiling"]["with_rows"]["best_us"] / rec["stage1_us"], 3)
                 for c in copies:  # every copy's y back to a full product
                     plan.execute(*c)
                 if kind == "f64":
@@ -415,24 +417,37 @@ def gather_ceiling(torch, sss, copies, alg: int, steps: int, warmup: int) -> dic
     """The device's rate for the reads of a CSR SpMV on this matrix with
     none of the method's choices (sss_gather_probe with val streamed: col and
     val coalesced, x gathered), over a set of issue modes, depths and
-    occupancies; the best reading is the design-independent ceiling."""
+    occupancies; the best reading is the design-independent ceiling.  Each
+    configuration is also timed with the row part (sss_gather_probe_rows:
+    row_ptr read, y written), which moves every algorithmic byte; that
+    ceiling matters where rows are short.  The copies' y are overwritten."""
     xdt = copies[0][3].dtype
     with_val = copies[0][2].dtype == xdt  # the probe streams val only when it shares x's type
     out_buf = torch.empty(1 << 20, dtype=xdt, device="cuda")
-    res = {}
+    res, res_rows = {}, {}
     for mode, U, wps in PROBE_CONFIGS:
         try:
             sss.gather_probe(copies[0][1], copies[0][3], out_buf, copies[0][2] if with_val else None, mode, U, wps)
         except sss.SSSError:
             continue
+        name = f"{sss.GATHER_MODES[mode & 3]}{'_chunked' if mode & 4 else ''}_u{U}_w{wps}"
         us = events_us(torch, lambda c: sss.gather_probe(c[1], c[3], out_buf, c[2] if with_val else None, mode, U, wps),
                        copies, steps, warmup)
-        res[f"{sss.GATHER_MODES[mode & 3]}{'_chunked' if mode & 4 else ''}_u{U}_w{wps}"] = round(us, 2)
+        res[name] = round(us, 2)
+        for after in (0, 8):  # rows spread over the gathers, or after them
+            us = events_us(torch, lambda c: sss.gather_probe(c[1], c[3], out_buf, c[2] if with_val else None,
+                                                             mode | after, U, wps, row_ptr=c[0], y=c[4]),
+                           copies, steps, warmup)
+            res_rows[name + ("_rows_after" if after else "_rows_spread")] = round(us, 2)
     del out_buf
     best = min(res, key=res.get)
+    best_r = min(res_rows, key=res_rows.get)
     return {"probe_us": res, "val_streamed": with_val, "best": best, "best_us": res[best],
             "best_alg_GBps": round(alg / (res[best] * 1e-6) / 1e9, 1),
-            "best_frac_of_peak": round(alg / (res[best] * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4)}
+            "best_frac_of_peak": round(alg / (res[best] * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4),
+            "with_rows": {"probe_us": res_rows, "best": best_r, "best_us": res_rows[best_r],
+                          "best_alg_GBps": round(alg / (res_rows[best_r] * 1e-6) / 1e9, 1),
+                          "best_frac_of_peak": round(alg / (res_rows[best_r] * 1e-6) / 1e9 / PEAK_HBM_GBPS, 4)}}
 
 
 def stencil_block(torch, sss, steps: int, warmup: int) -> dict:
@@ -531,6 +546,8 @@ def classes_block(torch, sss, steps: int, warmup: int) -> dict:
                     "stage1_frac_of_own_floor": round(fg / s1, 3),
                     "stage1_frac_of_probe_ceiling": round(ceil["best_us"] / s1, 3),
                     "probe_ceiling_frac_of_peak": ceil["best_frac_of_peak"],
+                    "stage1_frac_of_probe_ceiling_with_rows": round(ceil["with_rows"]["best_us"] / s1, 3),
+                    "probe_ceiling_with_rows_frac_of_peak": ceil["with_rows"]["best_frac_of_peak"],
                     "grid_us_by_class": {f"W{sss.class_params(c)[0]}S{sss.class_params(c)[1]}": round(float(t), 2)
                                          for c, t in enumerate(grid)},
                     "grid_best": "W{}S{}".format(*sss.class_params(best))}
@@ -603,12 +620,30 @@ def cg_block(torch, sss, iters: int = 300) -> dict:
     s1_us = graph_time_us(torch, lambda c: plan.stage1(*c), [(rp, col, v, x_true, y)])
     fo = torch.empty(plan.info()["n_bunches"] * 64, dtype=torch.float64, device="cuda")
     fl_us = graph_time_us(torch, lambda c: plan.floor_probe(c[1], c[2], c[3], fo, True), [(rp, col, v, x_true, y)])
+    # the design-independent probe moving every algorithmic byte (col, val, x,
+    # row_ptr, y), best over the probe configurations
+    pout = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+    probe_us = {}
+    for mode, U, wps in PROBE_CONFIGS:
+        try:
+            sss.gather_probe(col, x_true, pout, v, mode, U, wps, row_ptr=rp, y=y)
+        except sss.SSSError:
+            continue
+        for after in (0, 8):
+            name = f"{sss.GATHER_MODES[mode & 3]}{'_chunked' if mode & 4 else ''}_u{U}_w{wps}"
+            probe_us[name + ("_rows_after" if after else "_rows_spread")] = graph_time_us(
+                torch, lambda c: sss.gather_probe(c[1], c[3], pout, c[2], mode | after, U, wps, row_ptr=c[0],
+                                                  y=c[4]), [(rp, col, v, x_true, y)])
+    del pout
+    best_probe = min(probe_us, key=probe_us.get)
     byts = alg_bytes(A.m, A.n, A.nnz, 8, 8)
     out = {"workload": "laplacian2d_1024", "m": A.m, "nnz": A.nnz, "W": info["W"], "S": info["S"],
            "plan_ms": round(t_plan_ms, 3),
            "iterations": it, "us_per_iteration": round(it_us, 2), "spmv_us": round(spmv_us, 2),
            "spmv_alg_GBps": round(byts / (spmv_us * 1e-6) / 1e9, 1), "stage1_us": round(s1_us, 2),
            "stream_gather_floor_us": round(fl_us, 2),
+           "probe_with_rows_best": best_probe, "probe_with_rows_us": round(probe_us[best_probe], 2),
+           "stage1_frac_of_probe_with_rows": round(probe_us[best_probe] / s1_us, 3),
            "spmv_share": round(spmv_us / it_us, 3), "rel_residual": hist[-1][1],
            "rel_error": float(torch.linalg.vector_norm(x - x_true) / torch.linalg.vector_norm(x_true))}
     plan.close()
@@ -1029,6 +1064,7 @@ def main():
     if not args.skip_extras:
         ceiling = gather_ceiling(torch, sss, copies, alg_bytes(m, n, nnz, 8, 8), args.steps, args.warmup)
         ceiling["stage1_frac_of_ceiling"] = round(ceiling["best_us"] / (s1_ms * 1e3), 3)
+        ceiling["stage1_frac_of_ceiling_with_rows"] = round(ceiling["with_rows"]["best_us"] / (s1_ms * 1e3), 3)
         log(f"[bench] gather ceiling: {ceiling}")
 
     # the paper's comparison (Section 4.3) on this matrix: row-wise kernels

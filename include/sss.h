@@ -412,6 +412,18 @@ int sss_batch_floor_probe(sss_plan p, void *out, int gather, void *stream);
 int sss_gather_probe(const int32_t *col, const void *val, const void *x, int64_t nnz, int64_t n, sss_dtype dt,
                      int mode, int unroll, int waves_per_simd, int with_val, void *out, int64_t out_len,
                      int64_t *threads, int *resident_per_cu, void *stream);
+/* The same probe plus the row part of a CSR SpMV's bytes: with row_ptr
+ * non-NULL it also reads row_ptr[0..m] (device int32, m + 1 entries) and
+ * writes y[r] = row_ptr[r] for r < m (device, the x type), both coalesced in
+ * a grid-stride loop, so the probe moves every byte the product moves (col,
+ * val, x, row_ptr, y).  The rows go in batches of 8 per thread (loads before
+ * stores), spread over the gather loop; mode plus 8 puts them all after it
+ * instead.  row_ptr NULL is sss_gather_probe.  INVALID for m < 0, m above
+ * SSS_MAX_INDEX, or m > 0 with y NULL. */
+int sss_gather_probe_rows(const int32_t *col, const void *val, const void *x, int64_t nnz, int64_t n, sss_dtype dt,
+                          int mode, int unroll, int waves_per_simd, int with_val, void *out, int64_t out_len,
+                          int64_t *threads, int *resident_per_cu, const int32_t *row_ptr, int64_t m, void *y,
+                          void *stream);
 const char *sss_probe_last_hip_error(void);
 
 /* GRID-mode plan (the selector's fallback, and the yardstick of its regret):

@@ -16,7 +16,12 @@
 //   mode 2: direct-to-LDS loads (global_load_lds_dword): a gather in flight
 //           holds no VGPR; each wave reads its lanes' values back from LDS;
 //   mode 3: buffer loads at device scope (sc1), which the CU's L1 does not keep.
-// Each thread writes one sum, so no load can be dropped.
+// Each thread writes one sum, so no load can be dropped.  Optionally the same
+// kernel also moves the row part of a CSR SpMV's bytes, which the gathers do
+// not: it reads row_ptr (m + 1 entries) and writes one value per row of y,
+// both coalesced in a grid-stride loop interleaved with the gathers, so that
+// a matrix with short rows is measured against every byte the product itself
+// must move.
 
 #include <hip/hip_runtime.h>
 
@@ -29,6 +34,7 @@ namespace {
 constexpr int kProbeThreads = 256;  // 4 wavefronts per workgroup
 constexpr int kWaveP = 64;
 constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr int kRowsInFlight = 8;  // row_ptr loads per thread before its y stores
 
 thread_local hipError_t g_probe_hip = hipSuccess;
 
@@ -108,7 +114,9 @@ template <typename XT, int U, int MODE, bool WITH_VAL, bool CHUNKED>
 __global__ __launch_bounds__(kProbeThreads) void sss_gather_probe_kernel(const int32_t *__restrict__ col,
                                                                          const XT *__restrict__ val,
                                                                          const XT *__restrict__ x, int64_t nnz,
-                                                                         int64_t n, XT *__restrict__ out) {
+                                                                         int64_t n, XT *__restrict__ out,
+                                                                         const int32_t *__restrict__ rp, int64_t m,
+                                                                         XT *__restrict__ y, int rows_after) {
   extern __shared__ uint32_t lds_probe[];
   const int lane = threadIdx.x & (kWaveP - 1);
   uint32_t *lds_wave = lds_probe + (threadIdx.x / kWaveP) * (U * Words<XT>::n * kWaveP);
@@ -126,16 +134,47 @@ __global__ __launch_bounds__(kProbeThreads) void sss_gather_probe_kernel(const i
   }
   XT acc = 0;
   int64_t k = begin + lane;
+  // the row part (row_ptr read once, y written once, over the whole grid) in
+  // batches of kRowsInFlight rows per thread, loads before stores; the
+  // batches are spread over the nonzero groups, so that row and gather
+  // traffic share the run as they do in a product, or (rows_after) all follow
+  // the gathers
+  const int64_t rows_step = (int64_t)kRowsInFlight * threads;
+  const int64_t n_rb = rp ? (m + rows_step) / rows_step : 0;  // ceil((m + 1) / rows_step)
+  const bool spread = n_rb > 0 && !rows_after;
+  const int64_t n_groups = (end - begin + (int64_t)U * stride - 1) / ((int64_t)U * stride);
+  int64_t rb = 0, g = 0;
+  auto row_batches = [&](int64_t upto) {
+    for (; rb < upto; ++rb) {
+      const int64_t r0 = t + rb * rows_step;
+      int32_t v[kRowsInFlight];
+#pragma unroll
+      for (int u = 0; u < kRowsInFlight; ++u) {
+        const int64_t r = r0 + u * threads;
+        v[u] = r <= m ? rp[r] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRowsInFlight; ++u) {
+        const int64_t r = r0 + u * threads;
+        if (r < m) y[r] = (XT)v[u];
+        else if (r == m) acc += (XT)v[u];
+      }
+    }
+  };
   // full groups: the group's last iteration is inside for every lane of the
   // wave when it is for the wave's last lane, so the LDS path stays
   // wave-uniform
   for (int64_t wave_last = begin + (kWaveP - 1); wave_last + (int64_t)(U - 1) * stride < end;
-       wave_last += (int64_t)U * stride, k += (int64_t)U * stride)
+       wave_last += (int64_t)U * stride, k += (int64_t)U * stride) {
     acc += probe_group<XT, U, MODE, WITH_VAL>(col, val, x, rsrc, k, stride, lds_wave, lane);
+    ++g;
+    if (spread) row_batches((g * n_rb + n_groups - 1) / n_groups);
+  }
   for (; k < end; k += stride) {
     const XT v = x[col[k]];
     acc += WITH_VAL ? val[k] * v : v;
   }
+  row_batches(n_rb);
   out[t] = acc;
 }
 
@@ -172,16 +211,19 @@ const void *pick_kernel(int mode, int U, bool with_val, bool chunked) {
 
 extern "C" {
 
-int sss_gather_probe(const int32_t *col, const void *val, const void *x, int64_t nnz, int64_t n, sss_dtype dt,
-                     int mode, int unroll, int waves_per_simd, int with_val, void *out, int64_t out_len,
-                     int64_t *threads, int *resident_per_cu, void *stream) {
+int sss_gather_probe_rows(const int32_t *col, const void *val, const void *x, int64_t nnz, int64_t n, sss_dtype dt,
+                          int mode, int unroll, int waves_per_simd, int with_val, void *out, int64_t out_len,
+                          int64_t *threads, int *resident_per_cu, const int32_t *row_ptr, int64_t m, void *y,
+                          void *stream) {
   if (nnz < 0 || n < 1 || nnz > SSS_MAX_INDEX || n > SSS_MAX_INDEX / 8 || !col || !x || !out || !threads ||
-      (with_val && !val))
+      (with_val && !val) || (row_ptr && (m < 0 || m > SSS_MAX_INDEX || (m > 0 && !y))))
     return SSS_ERR_INVALID_VALUE;
+  if (!row_ptr) { m = 0; y = nullptr; }
   if (dt != SSS_F64 && dt != SSS_F32) return SSS_ERR_UNSUPPORTED;
   if (!(waves_per_simd == 1 || waves_per_simd == 2 || waves_per_simd == 4 || waves_per_simd == 8))
     return SSS_ERR_INVALID_VALUE;
   const bool chunked = (mode & 4) != 0;
+  int rows_after = (mode & 8) != 0;
   mode &= 3;
   const void *k = dt == SSS_F64 ? pick_kernel<double>(mode, unroll, with_val != 0, chunked)
                                 : pick_kernel<float>(mode, unroll, with_val != 0, chunked);
@@ -208,10 +250,17 @@ int sss_gather_probe(const int32_t *col, const void *val, const void *x, int64_t
   *threads = blocks * kProbeThreads;
   if (out_len < *threads) return SSS_ERR_INVALID_VALUE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  void *args[] = {&col, &val, &x, &nnz, &n, &out};
+  void *args[] = {&col, &val, &x, &nnz, &n, &out, &row_ptr, &m, &y, &rows_after};
   e = hipLaunchKernel(k, dim3((unsigned)blocks), dim3(kProbeThreads), args, lds, s);
   if (e != hipSuccess) { g_probe_hip = e; return SSS_ERR_HIP; }
   return SSS_OK;
+}
+
+int sss_gather_probe(const int32_t *col, const void *val, const void *x, int64_t nnz, int64_t n, sss_dtype dt,
+                     int mode, int unroll, int waves_per_simd, int with_val, void *out, int64_t out_len,
+                     int64_t *threads, int *resident_per_cu, void *stream) {
+  return sss_gather_probe_rows(col, val, x, nnz, n, dt, mode, unroll, waves_per_simd, with_val, out, out_len, threads,
+                               resident_per_cu, nullptr, 0, nullptr, stream);
 }
 
 const char *sss_probe_last_hip_error(void) { return hipGetErrorString(g_probe_hip); }

@@ -88,6 +88,8 @@ def lib():
         L.sss_floor_probe.argtypes = [P, P, P, P, P, I, P]
         L.sss_gather_probe.argtypes = [P, P, P, I64, I64, I, I, I, I, I, P, I64, ctypes.POINTER(I64),
                                        ctypes.POINTER(I), P]
+        L.sss_gather_probe_rows.argtypes = [P, P, P, I64, I64, I, I, I, I, I, P, I64, ctypes.POINTER(I64),
+                                            ctypes.POINTER(I), P, I64, P, P]
         L.sss_probe_last_hip_error.restype = ctypes.c_char_p
         L.sss_csr_spmv_stage2_host.argtypes = [P, P, P]
         L.sss_csr_rowwise.argtypes = [I64, I64, I64, P, P, P, P, P, I, I, P]
@@ -120,7 +122,7 @@ def lib():
                   "sss_plan_dirty_list", "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch", "sss_batch_floor_probe",
                   "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_csr_spmv_stage2_host", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
-                  "sss_selector_loaded", "sss_gather_probe", "sss_batch_plan_schedule", "sss_selector_scores"):
+                  "sss_selector_loaded", "sss_gather_probe", "sss_gather_probe_rows", "sss_batch_plan_schedule", "sss_selector_scores"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -417,17 +419,26 @@ GATHER_MODES = {0: "vector", 1: "nontemporal", 2: "lds_direct", 3: "buffer_sc1"}
 
 
 def gather_probe(col: torch.Tensor, x: torch.Tensor, out: torch.Tensor, val: Optional[torch.Tensor] = None,
-                 mode: int = 0, unroll: int = 8, waves_per_simd: int = 8, stream=None):
+                 mode: int = 0, unroll: int = 8, waves_per_simd: int = 8, stream=None,
+                 row_ptr: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None):
     """The device's random-gather rate (sss_gather_probe): one nonzero per
-    lane per grid-stride iteration, `unroll` gathers in flight.  Returns
-    (threads, resident workgroups per CU); out needs >= threads entries."""
+    lane per grid-stride iteration, `unroll` gathers in flight; with row_ptr
+    and y also the row part (sss_gather_probe_rows: row_ptr read, y written).
+    Returns (threads, resident workgroups per CU); out needs >= threads
+    entries."""
     dt = _DTYPES[x.dtype]
     if val is not None and val.dtype != x.dtype:
         raise TypeError("val and x must share a type")
     th, res = ctypes.c_int64(), ctypes.c_int()
-    _check(lib().sss_gather_probe(_ptr(col), _ptr(val), _ptr(x), col.numel(), x.numel(), dt, int(mode), int(unroll),
-                                  int(waves_per_simd), 1 if val is not None else 0, _ptr(out), out.numel(),
-                                  ctypes.byref(th), ctypes.byref(res), _stream(stream)), "sss_gather_probe")
+    args = (_ptr(col), _ptr(val), _ptr(x), col.numel(), x.numel(), dt, int(mode), int(unroll), int(waves_per_simd),
+            1 if val is not None else 0, _ptr(out), out.numel(), ctypes.byref(th), ctypes.byref(res))
+    if row_ptr is None:
+        _check(lib().sss_gather_probe(*args, _stream(stream)), "sss_gather_probe")
+    else:
+        if y is None or y.dtype != x.dtype or y.numel() < row_ptr.numel() - 1:
+            raise TypeError("y must be x's type with one entry per row")
+        _check(lib().sss_gather_probe_rows(*args, _ptr(row_ptr), row_ptr.numel() - 1, _ptr(y), _stream(stream)),
+               "sss_gather_probe_rows")
     return th.value, res.value
 
 

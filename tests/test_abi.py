@@ -79,6 +79,13 @@ def test_host_side_argument_checks():
     assert L.sss_csr_spmv_stage2_host(None, None, None) == -1
     n = ctypes.c_int64()
     assert L.sss_plan_dirty_list(None, None, 0, ctypes.byref(n)) == -1
+    # the probe's row part: a bad row count, or rows without y (pointers
+    # that are never dereferenced: the checks come first)
+    fake = ctypes.c_void_p(256)
+    assert L.sss_gather_probe_rows(fake, None, fake, 10, 10, 0, 0, 1, 4, 0, fake, 1 << 20, ctypes.byref(n), None,
+                                   fake, -1, fake, None) == -1
+    assert L.sss_gather_probe_rows(fake, None, fake, 10, 10, 0, 0, 1, 4, 0, fake, 1 << 20, ctypes.byref(n), None,
+                                   fake, 5, None, None) == -1
     assert L.sss_plan_destroy(None) == 0
 
 

@@ -316,6 +316,35 @@ def test_floor_probe_reads_every_nonzero_once(torch_cuda, WS):
     assert float(out.sum()) == float(np.sum(A.val + A.col))
 
 
+@pytest.mark.parametrize("mode_u_w", [(0, 4, 4), (0, 16, 8), (4, 16, 2), (2, 8, 1)])
+def test_gather_probe_reads_every_nonzero_and_row_once(torch_cuda, mode_u_w):
+    """The design-independent probe reads the matrix exactly once: on
+    integer-valued data its per-thread sums add up to sum_k val[k] x[col[k]];
+    with the row part they add row_ptr[m] too, and y holds row_ptr[0..m-1]."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    mode, U, wps = mode_u_w
+    # config 1, and 5M short or empty rows: more rows than one batch of 8 per
+    # thread covers, so several row batches are spread over the gather loop
+    for A, x in (csrgen.config1(int_valued=True),
+                 csr_from_lengths(np.random.default_rng(4).integers(0, 3, size=5_000_000), 50_000, seed=4)):
+        _check_gather_probe(torch, sss, A, x, mode, U, wps)
+
+
+def _check_gather_probe(torch, sss, A, x, mode, U, wps):
+    rp, col, v, xx = to_dev(A, x)
+    out = torch.full((1 << 20,), float("nan"), dtype=torch.float64, device="cuda")
+    th, _ = sss.gather_probe(col, xx, out, v, mode, U, wps)
+    torch.cuda.synchronize()
+    assert float(out[:th].sum()) == float(np.sum(A.val * x[A.col]))
+    for after in (0, 8):  # rows spread over the gathers, or after them
+        y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+        th, _ = sss.gather_probe(col, xx, out, v, mode | after, U, wps, row_ptr=rp, y=y)
+        torch.cuda.synchronize()
+        assert float(out[:th].sum()) == float(np.sum(A.val * x[A.col])) + float(A.row_ptr[-1])
+        assert np.array_equal(y.cpu().numpy(), A.row_ptr[:-1].astype(np.float64))
+
+
 @pytest.mark.parametrize("name", sorted(EDGE) + ["config1"])
 @pytest.mark.parametrize("WS", [(4, 1), (8, 5), (16, 2)])
 def test_bound_rows_plan(torch_cuda, name, WS):
