@@ -220,6 +220,12 @@ __device__ __forceinline__ int wave_prev(int v, int first) {
 }
 // v of lane `l`, for a lane index the same in every lane
 __device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// a 64-bit value the same in every lane, in scalar registers
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // *p for an address the same in every lane, of data no kernel of the launch
 // writes (plan arrays written before it): read through the scalar unit into
@@ -867,7 +873,7 @@ __device__ __forceinline__ void batch_entry(const BatchArgs &b, int64_t g, int4 
     bi = b.bunch_info[g];
     a = b.mats[bi.x];
   } else {
-    bi = uniform_load(b.bunch_info + __builtin_amdgcn_readfirstlane((int)g));
+    bi = uniform_load(b.bunch_info + uniform_i64(g));
     a = uniform_load(b.mats + bi.x);
   }
 }
