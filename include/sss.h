@@ -416,7 +416,7 @@ int sss_gather_probe(const int32_t *col, const void *val, const void *x, int64_t
  * non-NULL it also reads row_ptr[0..m] (device int32, m + 1 entries) and
  * writes y[r] = row_ptr[r] for r < m (device, the x type), both coalesced in
  * a grid-stride loop, so the probe moves every byte the product moves (col,
- * val, x, row_ptr, y).  The rows go in batches of 8 per thread (loads before
+ * val, x, row_ptr, y).  The rows go in batches of 4 per thread (loads before
  * stores), spread over the gather loop; mode plus 8 puts them all after it
  * instead.  row_ptr NULL is sss_gather_probe.  INVALID for m < 0, m above
  * SSS_MAX_INDEX, or m > 0 with y NULL. */

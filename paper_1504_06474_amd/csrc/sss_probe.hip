@@ -34,7 +34,7 @@ namespace {
 constexpr int kProbeThreads = 256;  // 4 wavefronts per workgroup
 constexpr int kWaveP = 64;
 constexpr size_t kLdsPerCu = 160 * 1024;
-constexpr int kRowsInFlight = 8;  // row_ptr loads per thread before its y stores
+constexpr int kRowsInFlight = 4;  // row_ptr loads per thread before its y stores (8 cost the U = 16 instance two waves per SIMD)
 
 thread_local hipError_t g_probe_hip = hipSuccess;
 
@@ -109,8 +109,9 @@ __device__ __forceinline__ XT probe_group(const int32_t *__restrict__ col, const
 // CHUNKED = false: one grid-stride loop over all nonzeros (the whole grid
 // sweeps the matrix as one front).  CHUNKED = true: every wavefront sweeps
 // its own contiguous chunk of the nonzeros, 64 at a time (lane + 64 i), as a
-// thread-bunch of the method does.
-template <typename XT, int U, int MODE, bool WITH_VAL, bool CHUNKED>
+// thread-bunch of the method does.  ROWS: also the row part (its registers
+// would otherwise lower the occupancy of the instances without it).
+template <typename XT, int U, int MODE, bool WITH_VAL, bool CHUNKED, bool ROWS>
 __global__ __launch_bounds__(kProbeThreads) void sss_gather_probe_kernel(const int32_t *__restrict__ col,
                                                                          const XT *__restrict__ val,
                                                                          const XT *__restrict__ x, int64_t nnz,
@@ -140,11 +141,12 @@ __global__ __launch_bounds__(kProbeThreads) void sss_gather_probe_kernel(const i
   // traffic share the run as they do in a product, or (rows_after) all follow
   // the gathers
   const int64_t rows_step = (int64_t)kRowsInFlight * threads;
-  const int64_t n_rb = rp ? (m + rows_step) / rows_step : 0;  // ceil((m + 1) / rows_step)
+  const int64_t n_rb = ROWS ? (m + rows_step) / rows_step : 0;  // ceil((m + 1) / rows_step)
   const bool spread = n_rb > 0 && !rows_after;
   const int64_t n_groups = (end - begin + (int64_t)U * stride - 1) / ((int64_t)U * stride);
   int64_t rb = 0, g = 0;
   auto row_batches = [&](int64_t upto) {
+    if constexpr (!ROWS) return;
     for (; rb < upto; ++rb) {
       const int64_t r0 = t + rb * rows_step;
       int32_t v[kRowsInFlight];
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kProbeThreads) void sss_gather_probe_kernel(const i
        wave_last += (int64_t)U * stride, k += (int64_t)U * stride) {
     acc += probe_group<XT, U, MODE, WITH_VAL>(col, val, x, rsrc, k, stride, lds_wave, lane);
     ++g;
-    if (spread) row_batches((g * n_rb + n_groups - 1) / n_groups);
+    if (ROWS && spread) row_batches((g * n_rb + n_groups - 1) / n_groups);
   }
   for (; k < end; k += stride) {
     const XT v = x[col[k]];
@@ -178,33 +180,34 @@ __global__ __launch_bounds__(kProbeThreads) void sss_gather_probe_kernel(const i
   out[t] = acc;
 }
 
-template <typename XT, int MODE, bool WITH_VAL, bool CHUNKED>
+template <typename XT, int MODE, bool WITH_VAL, bool CHUNKED, bool ROWS>
 const void *pick_u(int U) {
   switch (U) {
-    case 1: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 1, MODE, WITH_VAL, CHUNKED>);
-    case 2: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 2, MODE, WITH_VAL, CHUNKED>);
-    case 4: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 4, MODE, WITH_VAL, CHUNKED>);
-    case 8: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 8, MODE, WITH_VAL, CHUNKED>);
-    case 16: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 16, MODE, WITH_VAL, CHUNKED>);
+    case 1: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 1, MODE, WITH_VAL, CHUNKED, ROWS>);
+    case 2: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 2, MODE, WITH_VAL, CHUNKED, ROWS>);
+    case 4: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 4, MODE, WITH_VAL, CHUNKED, ROWS>);
+    case 8: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 8, MODE, WITH_VAL, CHUNKED, ROWS>);
+    case 16: return reinterpret_cast<const void *>(sss_gather_probe_kernel<XT, 16, MODE, WITH_VAL, CHUNKED, ROWS>);
     default: return nullptr;
   }
 }
 
-template <typename XT, bool WITH_VAL, bool CHUNKED>
+template <typename XT, bool WITH_VAL, bool CHUNKED, bool ROWS>
 const void *pick_mode(int mode, int U) {
   switch (mode) {
-    case 0: return pick_u<XT, 0, WITH_VAL, CHUNKED>(U);
-    case 1: return pick_u<XT, 1, WITH_VAL, CHUNKED>(U);
-    case 2: return pick_u<XT, 2, WITH_VAL, CHUNKED>(U);
-    case 3: return pick_u<XT, 3, WITH_VAL, CHUNKED>(U);
+    case 0: return pick_u<XT, 0, WITH_VAL, CHUNKED, ROWS>(U);
+    case 1: return pick_u<XT, 1, WITH_VAL, CHUNKED, ROWS>(U);
+    case 2: return pick_u<XT, 2, WITH_VAL, CHUNKED, ROWS>(U);
+    case 3: return pick_u<XT, 3, WITH_VAL, CHUNKED, ROWS>(U);
     default: return nullptr;
   }
 }
 
-template <typename XT>
+template <typename XT, bool ROWS>
 const void *pick_kernel(int mode, int U, bool with_val, bool chunked) {
-  if (with_val) return chunked ? pick_mode<XT, true, true>(mode, U) : pick_mode<XT, true, false>(mode, U);
-  return chunked ? pick_mode<XT, false, true>(mode, U) : pick_mode<XT, false, false>(mode, U);
+  if (with_val)
+    return chunked ? pick_mode<XT, true, true, ROWS>(mode, U) : pick_mode<XT, true, false, ROWS>(mode, U);
+  return chunked ? pick_mode<XT, false, true, ROWS>(mode, U) : pick_mode<XT, false, false, ROWS>(mode, U);
 }
 
 }  // namespace
@@ -225,8 +228,11 @@ int sss_gather_probe_rows(const int32_t *col, const void *val, const void *x, in
   const bool chunked = (mode & 4) != 0;
   int rows_after = (mode & 8) != 0;
   mode &= 3;
-  const void *k = dt == SSS_F64 ? pick_kernel<double>(mode, unroll, with_val != 0, chunked)
-                                : pick_kernel<float>(mode, unroll, with_val != 0, chunked);
+  const bool rows = row_ptr != nullptr;
+  const void *k = dt == SSS_F64 ? (rows ? pick_kernel<double, true>(mode, unroll, with_val != 0, chunked)
+                                        : pick_kernel<double, false>(mode, unroll, with_val != 0, chunked))
+                                : (rows ? pick_kernel<float, true>(mode, unroll, with_val != 0, chunked)
+                                        : pick_kernel<float, false>(mode, unroll, with_val != 0, chunked));
   if (!k) return SSS_ERR_UNSUPPORTED;
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
