@@ -1766,6 +1766,9 @@ int sss_csr_spmv_stage2(sss_plan p, const int32_t *row_ptr, void *y, void *strea
   if (p->m == 0) return SSS_OK;
   if (!row_ptr || !y) return SSS_ERR_INVALID_VALUE;
   if (p->bind_rows && row_ptr != p->bound_row_ptr) return SSS_ERR_PLAN_MISMATCH;
+  int dev = -1;
+  SSS_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return SSS_ERR_PLAN_MISMATCH;
   return launch_stage2(p, row_ptr, y, static_cast<hipStream_t>(stream));
 }
 
@@ -1864,12 +1867,15 @@ int sss_plan_destroy(sss_plan p) {
   // hipFree waits for the device's outstanding work before it frees (so a
   // replay of the plan's graph has ended before the graph goes); a
   // caller-provided workspace stays with the caller
-  hipError_t e = hipSuccess;
-  if (p->owns_aux && p->aux) e = hipFree(p->aux);
-  if (e == hipSuccess && p->graph_exec) e = hipGraphExecDestroy(p->graph_exec);
-  if (e == hipSuccess && p->graph) e = hipGraphDestroy(p->graph);
-  if (e == hipSuccess && p->capture_stream) e = hipStreamDestroy(p->capture_stream);
-  if (e != hipSuccess) { g_last_hip = e; rc = SSS_ERR_HIP; }
+  // every resource is released even when an earlier release fails; the
+  // first failure is the one reported
+  hipError_t first = hipSuccess;
+  auto release = [&first](hipError_t e) { if (first == hipSuccess) first = e; };
+  if (p->owns_aux && p->aux) release(hipFree(p->aux));
+  if (p->graph_exec) release(hipGraphExecDestroy(p->graph_exec));
+  if (p->graph) release(hipGraphDestroy(p->graph));
+  if (p->capture_stream) release(hipStreamDestroy(p->capture_stream));
+  if (first != hipSuccess) { g_last_hip = first; rc = SSS_ERR_HIP; }
   delete p;
   return rc;
 }
@@ -1958,6 +1964,9 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
     tot_m += d.m; tot_n += d.n; tot_nnz += d.nnz; tot_tiles += c.n_tiles;
   }
   const int64_t nb_all = bb[(size_t)count], spec_all = sb[(size_t)count];
+  // global bunch indices are listed as int32 (the dirty list): more bunches
+  // than that is beyond any batch that fits in memory
+  if (nb_all > INT32_MAX) return SSS_ERR_INVALID_VALUE;
   size_t off = 0;
   const size_t o_mats = off; off = align256(off + sizeof(MatCtx) * (size_t)std::max(count, 1));
   const size_t o_bb = off; off = align256(off + sizeof(int64_t) * ((size_t)count + 1));
@@ -2119,8 +2128,15 @@ int sss_batch_graph_launch(sss_plan p, void *stream) {
       return rc;
     }
     if (e != hipSuccess) { g_last_hip = e; return SSS_ERR_HIP; }
+    const hipError_t ei = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      // nothing is kept: the next call captures again
+      (void)hipGraphDestroy(g);
+      p->graph_exec = nullptr;
+      g_last_hip = ei;
+      return SSS_ERR_HIP;
+    }
     p->graph = g;
-    SSS_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
   }
   SSS_HIP(hipGraphLaunch(p->graph_exec, static_cast<hipStream_t>(stream)));
   return SSS_OK;
