@@ -364,6 +364,7 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
  * give sub-wavefront groups; a row's lanes stride over it and reduce by
  * shuffles.  Plain sums (double for SSS_F64, float otherwise), no plan, no
  * allocation; y is overwritten.  Arguments as for execute; dt as for plans.
+ * SSS_ERR_INVALID_VALUE for m, n or nnz negative or above SSS_MAX_INDEX;
  * SSS_ERR_UNSUPPORTED for any other lanes_per_row. */
 int sss_csr_rowwise(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, const void *val,
                     const void *x, void *y, sss_dtype dt, int lanes_per_row, void *stream);

@@ -97,7 +97,8 @@ extern "C" {
 
 int sss_csr_rowwise(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, const void *val,
                     const void *x, void *y, sss_dtype dt, int lanes_per_row, void *stream) {
-  if (m < 0 || n < 0 || nnz < 0) return SSS_ERR_INVALID_VALUE;
+  if (m < 0 || n < 0 || nnz < 0 || m > SSS_MAX_INDEX || n > SSS_MAX_INDEX || nnz > SSS_MAX_INDEX)
+    return SSS_ERR_INVALID_VALUE;
   if (!(lanes_per_row >= 1 && lanes_per_row <= kWave && (lanes_per_row & (lanes_per_row - 1)) == 0))
     return SSS_ERR_UNSUPPORTED;
   if (m == 0) return SSS_OK;

@@ -64,6 +64,7 @@ def test_host_side_argument_checks():
     assert L.sss_csr_rowwise(10, 10, 10, None, None, None, None, None, 0, 128, None) == -2
     assert L.sss_csr_rowwise(0, 0, 0, None, None, None, None, None, 0, 64, None) == 0
     assert L.sss_csr_rowwise(10, 10, 10, None, None, None, None, None, 0, 64, None) == -1
+    assert L.sss_csr_rowwise(2147479552, 10, 10, None, None, None, None, None, 0, 64, None) == -1
     big = 2147479551  # SSS_MAX_INDEX
     assert L.sss_csr_spmv_plan_create(big + 1, 10, 10, None, 0, None, None, ctypes.byref(h)) == -1
     assert L.sss_csr_spmv_plan_create(10, 10, big + 1, None, 0, None, None, ctypes.byref(h)) == -1
