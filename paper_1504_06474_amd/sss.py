@@ -197,18 +197,28 @@ class Plan:
                                    ctypes.byref(nb)), "sss_plan_info")
         return {"W": W.value, "S": S.value, "B": B.value, "n_tiles": nt.value, "n_bunches": nb.value}
 
+    def _check_rows(self, row_ptr: torch.Tensor, y: torch.Tensor):
+        if row_ptr.dtype != torch.int32 or row_ptr.numel() != self.m + 1:
+            raise ValueError("row_ptr must be int32 with m + 1 entries")
+        if y.dtype != _XTYPE[self.dt] or y.numel() < self.m:
+            raise ValueError("y must be of the plan's y type with at least m entries")
+
+    def _check_arrays(self, row_ptr, col, val, x, y):
+        """The sizes and types the plan was made for (the C entry points
+        receive bare pointers and cannot check them)."""
+        self._check_rows(row_ptr, y)
+        if val.dtype != _VALTYPE[self.dt] or x.dtype != _XTYPE[self.dt]:
+            raise TypeError("val/x dtypes do not match the plan")
+        if col.dtype != torch.int32 or col.numel() < self.nnz or val.numel() < self.nnz:
+            raise ValueError("col (int32) and val must hold nnz entries")
+        if x.numel() < self.n:
+            raise ValueError("x too short")
+
     def execute(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,
                 y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         if y is None:
             y = torch.empty(self.m, dtype=_XTYPE[self.dt], device=x.device)
-        if val.dtype != _VALTYPE[self.dt] or x.dtype != _XTYPE[self.dt] or y.dtype != _XTYPE[self.dt]:
-            raise TypeError("val/x/y dtypes do not match the plan")
-        if row_ptr.dtype != torch.int32 or col.dtype != torch.int32:
-            raise TypeError("row_ptr and col must be int32")
-        if row_ptr.numel() != self.m + 1 or col.numel() < self.nnz or val.numel() < self.nnz:
-            raise ValueError("array sizes do not match the plan")
-        if x.numel() < self.n or y.numel() < self.m:
-            raise ValueError("x or y too short")
+        self._check_arrays(row_ptr, col, val, x, y)
         rc = lib().sss_csr_spmv_execute(self._h, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
                                         _stream(stream))
         _check(rc, "sss_csr_spmv_execute")
@@ -216,11 +226,13 @@ class Plan:
 
     def stage1(self, row_ptr, col, val, x, y, stream=None):
         """Speculative execution only (sss_csr_spmv_stage1)."""
+        self._check_arrays(row_ptr, col, val, x, y)
         _check(lib().sss_csr_spmv_stage1(self._h, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
                                          _stream(stream)), "sss_csr_spmv_stage1")
 
     def stage2(self, row_ptr, y, stream=None):
         """Checking prediction only (sss_csr_spmv_stage2)."""
+        self._check_rows(row_ptr, y)
         _check(lib().sss_csr_spmv_stage2(self._h, _ptr(row_ptr), _ptr(y), _stream(stream)), "sss_csr_spmv_stage2")
 
     def dirty_list(self) -> np.ndarray:

@@ -253,6 +253,36 @@ def test_misaligned_pointers_rejected(torch_cuda):
         plan.execute(rp, colx[1:], v, xx)
 
 
+def test_binding_checks_arrays_before_any_launch(torch_cuda):
+    """The C entry points take bare pointers; the binding refuses host
+    tensors, strided views, and arrays shorter or of another type than the
+    plan was made for, in execute and in each stage, before calling them."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config1()
+    rp, col, v, xx = to_dev(A, x)
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    plan = sss.Plan(A.m, A.n, A.nnz)
+    bad_calls = [
+        lambda: plan.execute(rp, col[:-1], v, xx, y),
+        lambda: plan.execute(rp, col, v, xx, y.cpu()),
+        lambda: plan.execute(rp, col, v, xx[:-1], y),
+        lambda: plan.stage1(rp, col, v[:-1], xx, y),
+        lambda: plan.stage1(rp, col, v.float(), xx, y),
+        lambda: plan.stage1(rp, col, v, xx, y[:-1]),
+        lambda: plan.stage2(rp[:-1], y),
+        lambda: plan.stage2(rp, y[:-1]),
+        lambda: plan.stage2(rp, torch.empty(2 * A.m, dtype=torch.float64, device="cuda")[::2]),
+    ]
+    for call in bad_calls:
+        with pytest.raises((ValueError, TypeError)):
+            call()
+    plan.execute(rp, col, v, xx, y)
+    torch.cuda.synchronize()
+    assert_f64_parity(y.cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, x),
+                      oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
+
+
 @pytest.mark.parametrize("WS,bind", [((8, 5), True), ((8, 5), False), ((4, 8), False), ((16, 2), True)])
 def test_config2_full_size_f64(torch_cuda, WS, bind):
     """The 1M-row power-law matrix: every row against the oracle; W=8, S=5
