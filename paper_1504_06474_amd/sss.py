@@ -143,6 +143,20 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return t.data_ptr() if t.numel() else None
 
 
+def _check_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: Optional[torch.Tensor],
+               y: Optional[torch.Tensor], n: int):
+    """The sizes a CSR call implies (m = row_ptr entries - 1, nnz = val
+    entries), checked before any pointer reaches the library."""
+    if row_ptr.dtype != torch.int32 or row_ptr.numel() < 1:
+        raise ValueError("row_ptr must be int32 with m + 1 entries")
+    if col.dtype != torch.int32 or col.numel() < val.numel():
+        raise ValueError("col must be int32 with at least nnz (= val's length) entries")
+    if x is not None and x.numel() < n:
+        raise ValueError("x must hold n entries")
+    if y is not None and y.numel() < row_ptr.numel() - 1:
+        raise ValueError("y must hold m entries")
+
+
 def _stream(stream) -> Optional[int]:
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -356,6 +370,7 @@ class BatchPlan:
             rp, col, val, x, y = mt["row_ptr"], mt["col"], mt["val"], mt["x"], mt["y"]
             if val.dtype != _VALTYPE[self.dt] or x.dtype != _XTYPE[self.dt] or y.dtype != _XTYPE[self.dt]:
                 raise TypeError("val/x/y dtypes do not match the batch dtype")
+            _check_csr(rp, col, val, x, y, int(mt["n"]))
             m = rp.numel() - 1
             d = descs[i]
             d.m, d.n, d.nnz = m, int(mt["n"]), int(val.numel())
@@ -410,6 +425,8 @@ def features(row_ptr: torch.Tensor, n: int, nnz: int, dtype=torch.float64, strea
     """The 8 selector features of a CSR matrix (sss_csr_features)."""
     f = (ctypes.c_float * N_FEATURES)()
     dt = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    if row_ptr.dtype != torch.int32 or row_ptr.numel() < 1:
+        raise ValueError("row_ptr must be int32 with m + 1 entries")
     _check(lib().sss_csr_features(row_ptr.numel() - 1, int(n), int(nnz), _ptr(row_ptr), dt, _stream(stream), f),
            "sss_csr_features")
     return np.array(f[:], dtype=np.float32)
@@ -421,6 +438,7 @@ def autotune(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None):
     t = (ctypes.c_float * N_CLASSES)()
     best = ctypes.c_int()
     dt = _DTYPES[val.dtype]
+    _check_csr(row_ptr, col, val, x, y, int(n))
     _check(lib().sss_csr_spmv_autotune(row_ptr.numel() - 1, int(n), val.numel(), _ptr(row_ptr), _ptr(col),
                                        _ptr(val), _ptr(x), _ptr(y), dt, int(reps), _stream(stream), t,
                                        ctypes.byref(best)), "sss_csr_spmv_autotune")
@@ -441,6 +459,8 @@ def gather_probe(col: torch.Tensor, x: torch.Tensor, out: torch.Tensor, val: Opt
     dt = _DTYPES[x.dtype]
     if val is not None and val.dtype != x.dtype:
         raise TypeError("val and x must share a type")
+    if col.dtype != torch.int32 or (val is not None and val.numel() < col.numel()):
+        raise ValueError("col must be int32, and val at least as long")
     th, res = ctypes.c_int64(), ctypes.c_int()
     args = (_ptr(col), _ptr(val), _ptr(x), col.numel(), x.numel(), dt, int(mode), int(unroll), int(waves_per_simd),
             1 if val is not None else 0, _ptr(out), out.numel(), ctypes.byref(th), ctypes.byref(res))
@@ -457,6 +477,7 @@ def gather_probe(col: torch.Tensor, x: torch.Tensor, out: torch.Tensor, val: Opt
 def csr_rowwise(row_ptr, col, val, x, y, n: int, lanes_per_row: int, stream=None):
     """Row-wise comparator, not the method (sss_csr_rowwise): 1 lane per row
     is CSR-scalar, 64 is CSR-vector."""
+    _check_csr(row_ptr, col, val, x, y, int(n))
     _check(lib().sss_csr_rowwise(row_ptr.numel() - 1, int(n), val.numel(), _ptr(row_ptr), _ptr(col), _ptr(val),
                                  _ptr(x), _ptr(y), _DTYPES[val.dtype], int(lanes_per_row), _stream(stream)),
            "sss_csr_rowwise")
@@ -468,6 +489,7 @@ def plan_grid(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None) -> "P
     (sss_csr_spmv_plan_create_grid; y is overwritten while timing)."""
     h = ctypes.c_void_p()
     dt = _DTYPES[val.dtype]
+    _check_csr(row_ptr, col, val, x, y, int(n))
     _check(lib().sss_csr_spmv_plan_create_grid(row_ptr.numel() - 1, int(n), val.numel(), _ptr(row_ptr), _ptr(col),
                                                _ptr(val), _ptr(x), _ptr(y), dt, int(reps), _stream(stream),
                                                ctypes.byref(h)), "sss_csr_spmv_plan_create_grid")
@@ -543,6 +565,7 @@ def csr_spmv(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: tor
     for t in (val, x, y):
         if t.dtype != torch.float64:
             raise TypeError("sss_csr_spmv is the double-precision form")
+    _check_csr(row_ptr, col, val, x, y, n)
     rc = lib().sss_csr_spmv(m, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y), _stream(stream))
     _check(rc, "sss_csr_spmv")
     return y
@@ -558,6 +581,7 @@ def csr_spmv_noalloc(row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor
     for t in (val, x, y):
         if t.dtype != torch.float64:
             raise TypeError("sss_csr_spmv_noalloc is the double-precision form")
+    _check_csr(row_ptr, col, val, x, y, n)
     rc = lib().sss_csr_spmv_noalloc(m, n, val.numel(), _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y),
                                     _stream(stream))
     _check(rc, "sss_csr_spmv_noalloc")
