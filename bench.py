@@ -775,11 +775,12 @@ def batched_block(torch, sss, steps: int, warmup: int) -> dict:
     return out
 
 
-def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
-    """The trained selector on held-out selector matrices (indices 2000.., not
-    trained on), each stored as FP64, FP32 and BF16: regret against the grid
-    timed here, gain over the default parameters of that value type; and its
-    pick for the benchmark matrix."""
+def selector_block(torch, sss, n_matrices: int, bench_matrix, n_large: int = 10) -> dict:
+    """The trained selector on held-out selector matrices (indices 2000..,
+    not trained on) and on held-out matrices of the set's large part (2e6 to
+    1.6e7 rows, indices 2360..), each stored as FP64, FP32 and BF16: regret
+    against the grid timed here, gain over the default parameters of that
+    value type; and its pick for the benchmark matrix."""
     from csrgen.torch_gen import selector_matrix_gpu
     if not sss.load_selector():
         return {"error": "no trained selector parameters"}
@@ -787,42 +788,56 @@ def selector_block(torch, sss, n_matrices: int, bench_matrix) -> dict:
     from paper_1504_06474_amd.selector_train import VALUE_TYPES, time_plan as t_plan
 
     gm = lambda a: float(np.exp(np.mean(np.log(a))))
-    acc = {k: {"ratios": [], "gains": [], "hits": 0, "misses": []} for k in VALUE_TYPES}
+
+    def evaluate(indices, by_class):
+        acc = {k: {"ratios": [], "gains": [], "hits": 0, "misses": []} for k in VALUE_TYPES}
+        for i in indices:
+            d = selector_matrix_gpu(i)
+            for kind, (vt, xt) in VALUE_TYPES.items():
+                a = acc[kind]
+                args = (d["row_ptr"], d["col"], d["val"].to(vt), d["x"].to(xt),
+                        torch.empty(d["m"], dtype=xt, device="cuda"))
+                grid, best = sss.autotune(*args, n=d["n"], reps=5)
+                cls = sss.selector_predict(sss.features(d["row_ptr"], d["n"], d["nnz"], vt))
+                W, S = sss.class_params(cls)
+                p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, bind_rows=True, row_ptr=d["row_ptr"])
+                p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, W=W, S=S, bind_rows=True,
+                                 row_ptr=d["row_ptr"])
+                t_def, t_sel = t_plan(p_def, args, 5), t_plan(p_sel, args, 5)
+                if by_class is not None and kind == "f64" and i < 2005:  # one matrix of each selector class
+                    by_class[d["cls"]] = dict(rowwise_comparison(torch, sss, [args], d["n"],
+                                                                 lambda c: p_sel.execute(*c)),
+                                              matrix=d["name"], m=d["m"], nnz=d["nnz"], sss_plan=[W, S])
+                p_def.close()
+                p_sel.close()
+                a["ratios"].append(grid[cls] / grid.min())
+                a["gains"].append(t_def / t_sel)
+                a["hits"] += int(cls == best)
+                if a["ratios"][-1] > 1.1:
+                    a["misses"].append({"i": i, "name": d["name"], "picked": [W, S],
+                                        "best": list(sss.class_params(best)),
+                                        "picked_us": round(float(grid[cls]), 1),
+                                        "best_us": round(float(grid.min()), 1)})
+                del args
+            del d
+        res = {}
+        for kind, a in acc.items():
+            res[kind] = {"regret_vs_grid": round(gm(a["ratios"]) - 1, 4), "gain_vs_default": round(gm(a["gains"]), 3),
+                         "top1": round(a["hits"] / len(indices), 3), "worst_ratio": round(float(max(a["ratios"])), 3),
+                         "picks_over_10pct": a["misses"]}
+        res["regret_vs_grid"] = round(gm([r for a in acc.values() for r in a["ratios"]]) - 1, 4)
+        res["gain_vs_default"] = round(gm([g for a in acc.values() for g in a["gains"]]), 3)
+        return res
+
     by_class = {}
-    for i in range(2000, 2000 + n_matrices):
-        d = selector_matrix_gpu(i)
-        for kind, (vt, xt) in VALUE_TYPES.items():
-            a = acc[kind]
-            args = (d["row_ptr"], d["col"], d["val"].to(vt), d["x"].to(xt),
-                    torch.empty(d["m"], dtype=xt, device="cuda"))
-            grid, best = sss.autotune(*args, n=d["n"], reps=5)
-            cls = sss.selector_predict(sss.features(d["row_ptr"], d["n"], d["nnz"], vt))
-            W, S = sss.class_params(cls)
-            p_def = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, bind_rows=True, row_ptr=d["row_ptr"])
-            p_sel = sss.Plan(d["m"], d["n"], d["nnz"], dtype=vt, W=W, S=S, bind_rows=True, row_ptr=d["row_ptr"])
-            t_def, t_sel = t_plan(p_def, args, 5), t_plan(p_sel, args, 5)
-            if kind == "f64" and i < 2005:  # one matrix of each selector class
-                by_class[d["cls"]] = dict(rowwise_comparison(torch, sss, [args], d["n"], lambda c: p_sel.execute(*c)),
-                                          matrix=d["name"], m=d["m"], nnz=d["nnz"], sss_plan=[W, S])
-            p_def.close()
-            p_sel.close()
-            a["ratios"].append(grid[cls] / grid.min())
-            a["gains"].append(t_def / t_sel)
-            a["hits"] += int(cls == best)
-            if a["ratios"][-1] > 1.1:
-                a["misses"].append({"i": i, "name": d["name"], "picked": [W, S],
-                                    "best": list(sss.class_params(best)), "picked_us": round(float(grid[cls]), 1),
-                                    "best_us": round(float(grid.min()), 1)})
-            del args
-        del d
     out = {"held_out_matrices": n_matrices, "vs_rowwise_by_class": by_class}
-    for kind, a in acc.items():
-        out[kind] = {"regret_vs_grid": round(gm(a["ratios"]) - 1, 4), "gain_vs_default": round(gm(a["gains"]), 3),
-                     "top1": round(a["hits"] / n_matrices, 3), "worst_ratio": round(float(max(a["ratios"])), 3),
-                     "picks_over_10pct": a["misses"]}
-    allr = [r for a in acc.values() for r in a["ratios"]]
-    out["regret_vs_grid"] = round(gm(allr) - 1, 4)
-    out["gain_vs_default"] = round(gm([g for a in acc.values() for g in a["gains"]]), 3)
+    out.update(evaluate(range(2000, 2000 + n_matrices), by_class))
+    if n_large:
+        import csrgen
+        from paper_1504_06474_amd.selector_train import LARGE_TRAIN
+        first = csrgen.SELECTOR_LARGE_BASE + LARGE_TRAIN  # the large part's held-out matrices
+        out["large"] = dict(held_out_matrices=n_large, rows="2e6..1.6e7",
+                            **evaluate(range(first, first + n_large), None))
     rp, col, v, xx, y, A = bench_matrix
     grid, best = sss.autotune(rp, col, v, xx, y, n=A.n, reps=5)
     cls = sss.selector_predict(sss.features(rp, A.n, A.nnz))

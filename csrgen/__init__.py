@@ -43,6 +43,8 @@ __all__ = [
     "dense_rows_csr",
     "selector_matrix",
     "SELECTOR_CLASSES",
+    "SELECTOR_LARGE_BASE",
+    "selector_range",
     "uniform_values",
     "integer_values",
     "lognormal_values",
@@ -419,19 +421,33 @@ def dense_rows_csr(m: int, seed: int, base_mean: float = 5.0, values: str = "uni
 
 
 SELECTOR_CLASSES = ("stencil2d", "stencil3d", "fem_band", "weblike", "dense_rows")
+# matrices 0..SELECTOR_LARGE_BASE-1 of the selector set have 1e4..2e6 rows,
+# the ones from SELECTOR_LARGE_BASE on 2e6..1.6e7 (sizes past one XCD's L2 and
+# past the Infinity Cache, where the best tile schedule changes again)
+SELECTOR_LARGE_BASE = 2200
+SELECTOR_RANGES = ((1e4, 2e6), (2e6, 1.6e7))
 
 
-def selector_matrix(i: int, seed0: int = 10000, m_lo: float = 1e4, m_hi: float = 2e6,
+def selector_range(i: int):
+    """Row range (m_lo, m_hi) of the i-th selector matrix."""
+    return SELECTOR_RANGES[0] if i < SELECTOR_LARGE_BASE else SELECTOR_RANGES[1]
+
+
+def selector_matrix(i: int, seed0: int = 10000, m_lo: float | None = None, m_hi: float | None = None,
                     values: str = "uniform") -> CSR:
-    """The i-th matrix of the selector set: class i mod 5, rows log-uniform."""
+    """The i-th matrix of the selector set: class i mod 5, rows log-uniform in
+    selector_range(i) unless m_lo / m_hi are given; stencil sides capped at
+    m_hi's square or cube root."""
+    lo, hi = selector_range(i)
+    m_lo, m_hi = (lo if m_lo is None else m_lo), (hi if m_hi is None else m_hi)
     rng = rng_for(seed0 + i)
     cls = SELECTOR_CLASSES[i % len(SELECTOR_CLASSES)]
     target = math.exp(rng.uniform(math.log(m_lo), math.log(m_hi)))
     seed = seed0 + i + 7_000_000
     if cls == "stencil2d":
-        return stencil2d_csr(max(2, min(1414, int(round(math.sqrt(target))))), seed, values)
+        return stencil2d_csr(max(2, min(int(m_hi ** 0.5), int(round(math.sqrt(target))))), seed, values)
     if cls == "stencil3d":
-        return stencil3d_csr(max(2, min(125, int(round(target ** (1.0 / 3.0))))), seed, values)
+        return stencil3d_csr(max(2, min(int(m_hi ** (1.0 / 3.0)), int(round(target ** (1.0 / 3.0))))), seed, values)
     if cls == "fem_band":
         return fem_band_csr(max(100, int(target)), seed, values=values)
     if cls == "weblike":

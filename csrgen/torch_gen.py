@@ -1,8 +1,8 @@
 """Device-side (PyTorch) generators of the selector's matrix classes.
 
 Same classes and parameter draws as ``csrgen.selector_matrix`` (class i mod 5,
-rows log-uniform in [1e4, 2e6], class parameters from numpy PCG64 with the
-matrix's seed); the arrays themselves are drawn on the GPU with a seeded
+rows log-uniform in ``selector_range(i)``, class parameters from numpy PCG64
+with the matrix's seed); the arrays themselves are drawn on the GPU with a seeded
 ``torch.Generator`` so that thousands of large matrices can be produced in
 seconds.  These inputs only feed the parameter selector's timings, never a
 parity check.  Holds none of the SpMV arithmetic.
@@ -14,7 +14,7 @@ import math
 import numpy as np
 import torch
 
-from . import SELECTOR_CLASSES, rng_for
+from . import SELECTOR_CLASSES, rng_for, selector_range
 
 
 def _finish(lengths: torch.Tensor, cols: torch.Tensor, n: int, gen: torch.Generator, name: str):
@@ -101,9 +101,12 @@ def _dense_rows(m: int, gen, device, k: int, dense_len: np.ndarray, base_mean=5.
     return _finish(L, torch.cat(pieces), m, gen, f"dense_rows_{m}")
 
 
-def selector_matrix_gpu(i: int, seed0: int = 10000, m_lo: float = 1e4, m_hi: float = 2e6, device="cuda"):
+def selector_matrix_gpu(i: int, seed0: int = 10000, m_lo: float | None = None, m_hi: float | None = None,
+                        device="cuda"):
     """The i-th selector matrix, drawn on the GPU.  Returns a dict of device
     tensors (row_ptr, col int32; val, x float64) and sizes."""
+    lo, hi = selector_range(i)
+    m_lo, m_hi = (lo if m_lo is None else m_lo), (hi if m_hi is None else m_hi)
     rng = rng_for(seed0 + i)
     cls = SELECTOR_CLASSES[i % len(SELECTOR_CLASSES)]
     target = math.exp(rng.uniform(math.log(m_lo), math.log(m_hi)))
@@ -111,9 +114,9 @@ def selector_matrix_gpu(i: int, seed0: int = 10000, m_lo: float = 1e4, m_hi: flo
     gen.manual_seed(seed0 + i + 7_000_000)
     with torch.no_grad():
         if cls == "stencil2d":
-            d = _stencil(max(2, min(1414, int(round(math.sqrt(target))))), 2, gen, device)
+            d = _stencil(max(2, min(int(m_hi ** 0.5), int(round(math.sqrt(target))))), 2, gen, device)
         elif cls == "stencil3d":
-            d = _stencil(max(2, min(125, int(round(target ** (1.0 / 3.0))))), 3, gen, device)
+            d = _stencil(max(2, min(int(m_hi ** (1.0 / 3.0)), int(round(target ** (1.0 / 3.0))))), 3, gen, device)
         elif cls == "fem_band":
             d = _fem_band(max(100, int(target)), gen, device)
         elif cls == "weblike":

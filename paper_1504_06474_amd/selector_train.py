@@ -1,7 +1,8 @@
 """Train and evaluate the tile/parameter selector on one GPU.
 
     python -m paper_1504_06474_amd.selector_train --out <out-dir> \
-        [--train 2000] [--test 200] [--reps 5] [--steps 4000]
+        [--train 2000] [--test 200] [--large-train 160] [--large-test 40] \
+        [--reps 5] [--steps 4000]
     python -m paper_1504_06474_amd.selector_train --out <out-dir> --collect A:B
     python -m paper_1504_06474_amd.selector_train --out <out-dir> --fit
 
@@ -12,20 +13,23 @@ file in <out-dir>.
 
 1. Data: matrices 0..train+test-1 of the selector set (2D 5-point and 3D
    27-point stencils, FEM-like bands, web-like lognormal rows, dense rows in a
-   sparse matrix; 1e4..2e6 rows), drawn on the GPU, each stored once per value
-   type (FP64, FP32, BF16).  For each sample: the 8 features
+   sparse matrix; 1e4..2e6 rows) and matrices L..L+large_train+large_test-1
+   of its large part (L = csrgen.SELECTOR_LARGE_BASE; 2e6..1.6e7 rows), drawn
+   on the GPU, each stored once per value type (FP64, FP32, BF16).  For each sample: the 8 features
    (sss_csr_features; the last is the bytes per stored value) and the median
    time of every (W, S) class of the grid (sss_csr_spmv_autotune, `reps` timed
    runs per trial, plans with bound rows), plus the time of the default
    parameters for that type (also with bound rows)
    (the paper's Table 3 choices for its AMD GPU: W = 8, S = 5 in double
    precision; W = 16, S = 2 in single).
-2. Training on the first `train` matrices: features z-scored, soft targets
+2. Training on the first `train` matrices of each part (`large_train` of the
+   large one): features z-scored, soft targets
    q_c ~ exp(-(t_c / t_best - 1) / tau), softmax cross-entropy, full-batch
    Adam -- forward, backward and update all by the library's HIP kernels.
-3. Evaluation on the last `test` matrices against the grid timed in the same
-   session: regret = geomean(t(selected) / t(grid best)) - 1, gain =
-   geomean(t(default) / t(selected)).
+3. Evaluation on the held-out rest of each part against the grid timed in
+   the same session: regret = geomean(t(selected) / t(grid best)) - 1, gain =
+   geomean(t(default) / t(selected)); reported over all held-out matrices and
+   for the large part alone.
 Writes selector_params.json (parameters, normalisation, class table) and
 selector_report.json (metrics, per-class breakdown) to --out; the dataset goes
 to dataset.npz there.
@@ -67,6 +71,10 @@ def time_plan(plan, args, reps: int, trials: int = 5) -> float:
     return float(np.median(ts))
 
 
+# matrices of the selector set's large part that train the shipped network;
+# the ones after them are held out
+LARGE_TRAIN = 160
+
 VALUE_TYPES = {"f64": (torch.float64, torch.float64), "f32": (torch.float32, torch.float32),
                "bf16": (torch.bfloat16, torch.float32)}  # (val, x and y)
 
@@ -76,7 +84,7 @@ def collect(indices, reps: int, dtypes=("f64", "f32", "bf16")):
     per-type default (W = 0, S = 0)."""
     from csrgen.torch_gen import selector_matrix_gpu
     feats, times, t_def, names, kinds, mats, sizes = [], [], [], [], [], [], []
-    t0 = time.time()
+    t0 = t_log = time.time()
     for k, i in enumerate(indices):
         d = selector_matrix_gpu(int(i))
         rp, col = d["row_ptr"], d["col"]
@@ -96,8 +104,9 @@ def collect(indices, reps: int, dtypes=("f64", "f32", "bf16")):
             sizes.append((d["m"], d["nnz"]))
             del val, x, y
         del d, rp, col
-        if (k + 1) % 50 == 0:
-            log(f"[selector] {k + 1}/{len(indices)} matrices timed ({time.time() - t0:.0f} s)")
+        if (k + 1) % 50 == 0 or time.time() - t_log > 30:
+            t_log = time.time()
+            log(f"[selector] {k + 1}/{len(indices)} matrices timed ({t_log - t0:.0f} s)")
     return (np.array(feats, dtype=np.float32), np.array(times), np.array(t_def), np.array(names),
             np.array(kinds), np.array(mats, dtype=np.int64), np.array(sizes, dtype=np.int64))
 
@@ -193,6 +202,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
+    ap.add_argument("--large-train", type=int, default=LARGE_TRAIN)
+    ap.add_argument("--large-test", type=int, default=40)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=3e-3)
@@ -205,7 +216,12 @@ def main():
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     sss.lib()
-    n_all = args.train + args.test
+    import csrgen
+    base = csrgen.SELECTOR_LARGE_BASE
+    if args.train + args.test > base:
+        raise SystemExit(f"--train + --test must stay below {base}, where the large part begins")
+    indices = list(range(args.train + args.test)) + list(range(base, base + args.large_train + args.large_test))
+    n_all = len(indices)
     dtypes = tuple(args.dtypes.split(","))
     keys = ("feats", "times", "t_default", "names", "kinds", "mats", "sizes")
     if args.collect:
@@ -219,14 +235,20 @@ def main():
         import glob
         parts = [np.load(f) for f in sorted(glob.glob(os.path.join(args.out, "part_*.npz")))]
         feats, times, t_def, names, kinds, mats, sizes = (np.concatenate([p[k] for p in parts]) for k in keys)
-        if sorted(set(mats.tolist())) != list(range(n_all)):
-            raise SystemExit(f"the part files cover {len(set(mats.tolist()))} of matrices 0..{n_all - 1}")
+        have = set(mats.tolist())
+        if not set(indices) <= have:
+            raise SystemExit(f"the part files cover {len(have & set(indices))} of the {n_all} matrices asked for")
+        keep = np.isin(mats, indices)
+        feats, times, t_def, names, kinds, mats, sizes = (a[keep] for a in (feats, times, t_def, names, kinds,
+                                                                              mats, sizes))
     else:
         log(f"[selector] timing {n_all} matrices x {dtypes}, {sss.N_CLASSES} classes, {args.reps} runs per trial")
-        feats, times, t_def, names, kinds, mats, sizes = collect(range(n_all), args.reps, dtypes)
+        feats, times, t_def, names, kinds, mats, sizes = collect(indices, args.reps, dtypes)
     np.savez(os.path.join(args.out, "dataset.npz"), feats=feats, times=times, t_default=t_def, names=names,
              kinds=kinds, mats=mats, sizes=sizes)
-    tr, te = mats < args.train, mats >= args.train
+    large = mats >= base
+    tr = np.where(large, mats < base + args.large_train, mats < args.train)
+    te = ~tr
     Xtr, Xte = feats[tr], feats[te]
     mean = Xtr.mean(axis=0)
     std = Xtr.std(axis=0)
@@ -235,17 +257,21 @@ def main():
     params, hist = train((Xtr - mean) / std, Q, args.steps, args.lr, args.seed)
     log(f"[selector] loss {hist}")
     res_tr = evaluate(predict(params, (Xtr - mean) / std), times[tr], t_def[tr], names[tr], kinds[tr])
-    res_te = evaluate(predict(params, (Xte - mean) / std), times[te], t_def[te], names[te], kinds[te])
+    pred_te = predict(params, (Xte - mean) / std)
+    res_te = evaluate(pred_te, times[te], t_def[te], names[te], kinds[te])
+    lte = large[te]
+    res_large = evaluate(pred_te[lte], times[te][lte], t_def[te][lte], names[te][lte], kinds[te][lte]) \
+        if lte.any() else None
     classes = [list(sss.class_params(c)) for c in range(sss.N_CLASSES)]
     json.dump({"params": [float(v) for v in params], "feature_mean": [float(v) for v in mean],
                "feature_std": [float(v) for v in std], "classes_WS": classes,
                "features": ["log2(m+1)", "log2(n+1)", "log2(nnz+1)", "log2(1+mean)", "log2(1+var)",
                             "log2(1+max)", "empty_frac", "bytes_per_value"],
-               "trained_on": f"selector matrices 0..{args.train - 1} (seed base 10000) as {'/'.join(dtypes)}, "
-                             f"T=64 B=2",
+               "trained_on": f"selector matrices 0..{args.train - 1} and {base}..{base + args.large_train - 1} "
+                             f"(seed base 10000) as {'/'.join(dtypes)}, T=64 B=2",
                "command": "python -m paper_1504_06474_amd.selector_train " + " ".join(sys.argv[1:])},
               open(os.path.join(args.out, "selector_params.json"), "w"))
-    report = {"train": res_tr, "test": res_te, "loss_history": hist, "args": vars(args),
+    report = {"train": res_tr, "test": res_te, "test_large": res_large, "loss_history": hist, "args": vars(args),
               "sweep_geomean_t_over_best": sweep(times, names, kinds),
               "class_best_counts": {k: np.bincount(times[kinds == k].argmin(axis=1), minlength=12).tolist()
                                     for k in dtypes}}
@@ -254,6 +280,10 @@ def main():
         f"(grid gain {res_te['grid_gain_vs_default']:.3f}) accuracy {res_te['accuracy']:.3f}")
     for k, v in res_te["per_value_type"].items():
         log(f"[selector]   {k}: regret {v['regret']:.4f} gain {v['gain_vs_default']:.3f} worst {v['worst_ratio']:.3f}")
+    if res_large:
+        log(f"[selector] large part ({res_large['n']} held-out samples): regret {res_large['regret']:.4f} "
+            f"gain {res_large['gain_vs_default']:.3f} (grid gain {res_large['grid_gain_vs_default']:.3f}) "
+            f"worst {res_large['worst_ratio']:.3f}")
 
 
 if __name__ == "__main__":

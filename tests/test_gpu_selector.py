@@ -47,16 +47,12 @@ def _time(torch, plan, args, reps=7):
     return time_plan(plan, args, reps) * 1e-3
 
 
-@pytest.mark.parametrize("kind", ["f64", "f32", "bf16"])
-def test_selector_gain_on_held_out(sel, kind):
-    """Held-out selector matrices (indices 2000.., never trained on), stored
-    as `kind`; the default plan is the library's default for that type."""
-    torch, sss = sel
+def _held_out_gain_and_regret(torch, sss, kind, indices):
     from csrgen.torch_gen import selector_matrix_gpu
     from paper_1504_06474_amd.selector_train import VALUE_TYPES
     vt, xt = VALUE_TYPES[kind]
     gains, regrets = [], []
-    for i in range(2000, 2015):
+    for i in indices:
         d = selector_matrix_gpu(i)
         args = (d["row_ptr"], d["col"], d["val"].to(vt), d["x"].to(xt), torch.empty(d["m"], dtype=xt, device="cuda"))
         # gain: selected vs default plan, both timed the same way
@@ -75,8 +71,31 @@ def test_selector_gain_on_held_out(sel, kind):
     g = float(np.exp(np.mean(np.log(gains))))
     r = float(np.exp(np.mean(np.log(regrets)))) - 1
     note(f"  geomean gain over default {g:.3f}, regret vs grid {r:.4f}")
+    return g, r
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32", "bf16"])
+def test_selector_gain_on_held_out(sel, kind):
+    """Held-out selector matrices (indices 2000.., never trained on), stored
+    as `kind`; the default plan is the library's default for that type."""
+    torch, sss = sel
+    g, r = _held_out_gain_and_regret(torch, sss, kind, range(2000, 2015))
     assert g > 1.1
     assert r <= 0.05  # the selector's target: within 5% of the autotuned grid
+
+
+def test_selector_on_held_out_large_matrices(sel):
+    """Held-out matrices of the selector set's large part (2e6..1.6e7 rows,
+    indices 2360.., never trained on; one of each class), FP64: within 5% of
+    the grid, and no slower than the default plan (whose S suits large
+    matrices, so there is little to gain there)."""
+    torch, sss = sel
+    import csrgen
+    from paper_1504_06474_amd.selector_train import LARGE_TRAIN
+    first = csrgen.SELECTOR_LARGE_BASE + LARGE_TRAIN
+    g, r = _held_out_gain_and_regret(torch, sss, "f64", range(first, first + 5))
+    assert r <= 0.05
+    assert g > 0.98
 
 
 def test_grid_plan(sel):
