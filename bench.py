@@ -119,7 +119,7 @@ def row_sums(row_ptr, col, val, x):
 
 
 def cpu_baseline(A, x, seconds: float) -> dict:
-    """The oracle on the host cores (the graded baseline), then the paper's
+    """The oracle on the host cores (the reported CPU baseline), then the paper's
     CPU comparators on the same matrix (Section 4.3): the oracle's Dot2 row
     loop on one thread, the plain OpenMP row-block loop, and the plain
     single-thread loop.  Each comparator gets a fifth of `seconds`."""

@@ -394,7 +394,7 @@ int sss_floor_probe(sss_plan p, const int32_t *col, const void *val, const void 
 int sss_batch_floor_probe(sss_plan p, void *out, int gather, void *stream);
 
 /* Measurement aid, not part of the method: how fast the device serves random
- * gathers x[col[k]] at all, with none of stage 1's choices (Section 4.4 judges
+ * gathers x[col[k]] at all, with none of stage 1's choices (Section 4.4 measures
  * the method by bandwidth utilisation; this is the ceiling the gathers put on
  * it).  A grid-stride loop gives every lane one nonzero per iteration
  * (k = thread + i * threads: col and val read coalesced) and keeps `unroll`
