@@ -16,7 +16,7 @@ kernels.
 import numpy as np
 import pytest
 
-from helpers import note
+from helpers import note, assert_f32_path_bound
 
 MAX_INDEX = 2147479551  # SSS_MAX_INDEX
 CHUNK = 1 << 27
@@ -134,6 +134,42 @@ def test_nnz_at_index_limit(torch_cuda):
             got = y.cpu().numpy()
             assert np.array_equal(got, want), (kw, bind, int(np.sum(got != want)))
             plan.close()
+    del col, val, y
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_nnz_at_index_limit_reduced_precision(torch_cuda, kind):
+    """The same matrix with FP32 or BF16 values (1 and 2 are exact in both)
+    and an FP32 x: rows whose sums stay below 2^24 come out exact, and every
+    row, the 108M-entry one included, within the reduced-precision path's
+    bound of 2u (|A||x|)_i against the exact product, (|A||x|)_i being the
+    same closed form over |x|."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    m, n, nnz = 1_048_573, 1_000_003, MAX_INDEX
+    rp = ragged_row_ptr(m, nnz, 31)
+    x = int_x(n, 32)
+    want = expected_y(rp, Prefix(x))
+    scale = expected_y(rp, Prefix(np.abs(x)))
+    vt = torch.float32 if kind == "f32" else torch.bfloat16
+    rp_d, x_d = torch.from_numpy(rp).cuda(), torch.from_numpy(x).float().cuda()
+    col = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    val = torch.empty(nnz, dtype=vt, device="cuda")
+    fill_entries(torch, col, val, n)
+    y = torch.empty(m, dtype=torch.float32, device="cuda")
+    for kw in ({}, {"W": 4, "S": 1, "B": 1}, {"W": 16, "S": 8, "B": 2}):
+        note(f"[gpu-test]   {kind} plan {kw}")
+        plan = sss.Plan(m, n, nnz, dtype=vt, bind_rows=True, row_ptr=rp_d, **kw)
+        y.fill_(float("nan"))
+        plan.execute(rp_d, col, val, x_d, y)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy().astype(np.float64)
+        small = np.abs(scale) < 2 ** 24
+        assert np.array_equal(got[small], want[small]), (kind, kw)
+        assert_f32_path_bound(got, want, scale, rp)
+        plan.close()
     del col, val, y
     torch.cuda.empty_cache()
 
