@@ -91,3 +91,28 @@ def test_fuzz_batched(seed):
     torch.cuda.synchronize()
     for d, ref in zip(descs, refs):
         assert_exact(d["y"].cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_fuzz_stage2_on_host(seed):
+    """The paper's split on random matrices: stage 1 on the device, then the
+    carries, the re-arrangement and the leading rows on a host core
+    (sss_csr_spmv_stage2_host), bit-exact against the oracle in FP64 and in
+    FP32."""
+    import torch
+    from paper_1504_06474_amd import sss
+    rng = np.random.default_rng(9000 + seed)
+    W = int(rng.choice([4, 8, 16]))
+    S = int(rng.integers(1, 17))
+    bind = bool(rng.integers(0, 2))
+    kind = ("f64", "f32")[int(rng.integers(0, 2))]
+    A, x = random_matrix(20_000 + seed, W)
+    note(f"  seed={seed} m={A.m} nnz={A.nnz} W={W} S={S} bind={bind} {kind}")
+    rp, col, v, xx, ve, xe = to_dev_precision(A, x, kind)
+    plan = sss.Plan(A.m, A.n, A.nnz, dtype=v.dtype, W=W, S=S, bind_rows=bind, row_ptr=rp if bind else None)
+    y = torch.full((A.m,), float("nan"), dtype=xx.dtype, device="cuda")
+    plan.stage1(rp, col, v, xx, y)
+    torch.cuda.synchronize()
+    y_host = y.cpu()
+    plan.stage2_host(A.row_ptr, y_host)
+    assert_exact(y_host.double().numpy(), oracle.spmv(A.row_ptr, A.col, ve, xe))
