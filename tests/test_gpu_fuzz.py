@@ -116,3 +116,32 @@ def test_fuzz_stage2_on_host(seed):
     y_host = y.cpu()
     plan.stage2_host(A.row_ptr, y_host)
     assert_exact(y_host.double().numpy(), oracle.spmv(A.row_ptr, A.col, ve, xe))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_fuzz_bound_plan_row_ptr_rewritten(seed):
+    """A plan bound to a row_ptr array whose contents are then replaced in
+    place by another structure with the same m and nnz (the row lengths
+    shuffled): stage 1 finds the stored first rows stale and searches again,
+    stage 2 takes the unlisted dirty bunches too; y stays exact, on two calls
+    in a row."""
+    import torch
+    from paper_1504_06474_amd import sss
+    rng = np.random.default_rng(12_000 + seed)
+    W = int(rng.choice([4, 8, 16]))
+    S = int(rng.integers(1, 17))
+    A, x = random_matrix(30_000 + seed, W)
+    lengths = np.diff(A.row_ptr.astype(np.int64))
+    A2 = csrgen.lengths_to_csr(rng, rng.permutation(lengths), A.n, "int")
+    note(f"  seed={seed} m={A.m} nnz={A.nnz} W={W} S={S}")
+    rp, col, v, xx = to_dev(A, x)
+    plan = sss.Plan(A.m, A.n, A.nnz, W=W, S=S, bind_rows=True, row_ptr=rp)
+    rp.copy_(torch.from_numpy(A2.row_ptr.astype(np.int32)).cuda())
+    col2 = torch.from_numpy(A2.col).cuda()
+    v2 = torch.from_numpy(A2.val).cuda()
+    want = oracle.spmv(A2.row_ptr, A2.col, A2.val, x)
+    for _ in range(2):
+        y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+        plan.execute(rp, col2, v2, xx, y)
+        torch.cuda.synchronize()
+        assert_exact(y.cpu().numpy(), want)
