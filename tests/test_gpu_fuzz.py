@@ -145,3 +145,38 @@ def test_fuzz_bound_plan_row_ptr_rewritten(seed):
         plan.execute(rp, col2, v2, xx, y)
         torch.cuda.synchronize()
         assert_exact(y.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_fuzz_execute_replayed_from_a_graph(seed):
+    """execute captured once into a graph on random matrices and types, then
+    replayed three times with a new x and y clobbered by the program's own
+    eager work in between: every replay is exact."""
+    import torch
+    from paper_1504_06474_amd import sss
+    rng = np.random.default_rng(15_000 + seed)
+    W = int(rng.choice([4, 8, 16]))
+    S = int(rng.integers(1, 17))
+    bind = bool(rng.integers(0, 2))
+    kind = ("f64", "f32", "bf16")[int(rng.integers(0, 3))]
+    A, x = random_matrix(40_000 + seed, W)
+    note(f"  seed={seed} m={A.m} nnz={A.nnz} W={W} S={S} bind={bind} {kind}")
+    rp, col, v, xx, ve, xe = to_dev_precision(A, x, kind)
+    plan = sss.Plan(A.m, A.n, A.nnz, dtype=v.dtype, W=W, S=S, bind_rows=bind, row_ptr=rp if bind else None)
+    y = torch.empty(A.m, dtype=xx.dtype, device="cuda")
+    plan.execute(rp, col, v, xx, y)  # first call outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(rp, col, v, xx, y)
+    for rep in range(3):
+        xh = csrgen.integer_values(rng, A.n)  # exact in every type
+        xx.copy_(torch.from_numpy(xh).to(xx.dtype))
+        y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_exact(y.double().cpu().numpy(), oracle.spmv(A.row_ptr, A.col, ve, xh))
+        plan.execute(rp, col, v, xx, y)  # eager work between replays
+        torch.cuda.synchronize()
+    del g
