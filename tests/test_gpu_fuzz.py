@@ -180,3 +180,35 @@ def test_fuzz_execute_replayed_from_a_graph(seed):
         plan.execute(rp, col, v, xx, y)  # eager work between replays
         torch.cuda.synchronize()
     del g
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_fuzz_batched_graph_replays(seed):
+    """Random batches run from the plan's own graph (sss_batch_graph_launch,
+    captured on the first call) three times, with every x rewritten and every
+    y clobbered by eager work in between: exact each time."""
+    import torch
+    from paper_1504_06474_amd import sss
+    rng = np.random.default_rng(18_000 + seed)
+    W = int(rng.choice([4, 8, 16]))
+    mats = [random_matrix(50_000 * (seed + 1) + i, W) for i in range(int(rng.integers(1, 16)))]
+    descs = []
+    for A, x in mats:
+        rp, col, v, xx = to_dev(A, x)
+        y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+        descs.append({"row_ptr": rp, "col": col, "val": v, "x": xx, "y": y, "n": A.n, "S": int(rng.integers(1, 17))})
+    persistent = bool(rng.integers(0, 2))
+    note(f"  seed={seed} matrices={len(mats)} W={W} persistent={persistent}")
+    plan = sss.BatchPlan(descs, W=W, persistent=persistent)
+    for rep in range(3):
+        xs = [csrgen.integer_values(rng, A.n) for A, _ in mats]
+        for d, xh in zip(descs, xs):
+            d["x"].copy_(torch.from_numpy(xh))
+            d["y"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.graph_launch()
+        torch.cuda.synchronize()
+        for d, (A, _), xh in zip(descs, mats, xs):
+            assert_exact(d["y"].cpu().numpy(), oracle.spmv(A.row_ptr, A.col, A.val, xh))
+        plan.execute()  # eager work between replays
+        torch.cuda.synchronize()
