@@ -21,6 +21,38 @@ def test_header_declares_entry_points():
         assert s in syms
 
 
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/sss.h is valid C99 on its own (no C++ or HIP types leak into
+    the boundary), and a C program using it links against libsss.so."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(
+        '#include "sss.h"\n'
+        "int spmv_many(int64_t m, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *col,\n"
+        "              const double *val, const double *x, double *y, void *stream, int calls) {\n"
+        "  sss_plan_opts opts = {0};\n"
+        "  opts.mode = SSS_MODE_FIXED;\n"
+        "  opts.bind_rows = 1;\n"
+        "  sss_plan plan = NULL;\n"
+        "  int rc = sss_csr_spmv_plan_create(m, n, nnz, rp, SSS_F64, &opts, stream, &plan);\n"
+        "  for (int k = 0; rc == SSS_OK && k < calls; ++k)\n"
+        "    rc = sss_csr_spmv_execute(plan, rp, col, val, x, y, stream);\n"
+        "  sss_plan_destroy(plan);\n"
+        "  return rc;\n"
+        "}\n"
+        "int main(void) { return sss_status_string(SSS_OK) ? 0 : 1; }\n")
+    lib_dir = os.path.join(ROOT, "paper_1504_06474_amd")
+    out = tmp_path / "use"
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), str(src), "-L", lib_dir, "-lsss",
+                        f"-Wl,-rpath,{lib_dir}", "-o", str(out)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1504_06474_amd import sss
     L = sss.lib()
