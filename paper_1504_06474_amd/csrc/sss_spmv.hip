@@ -848,6 +848,10 @@ __global__ __launch_bounds__(256) void sss_floor(MatCtx a, typename VT<DT>::y_t 
 // within the matrix from the plan (found at plan time by the same
 // rightmost-match search the method uses for rows); stage 2 runs that search
 // over bunch_base itself.
+// gfx950 (one partition) hands consecutive workgroups to its 8 XCDs in turn,
+// workgroup b to XCD b mod 8, and every XCD has its own L2.
+constexpr int kXcds = 8;
+
 struct BatchArgs {
   const MatCtx *mats;
   const int64_t *bunch_base;  // [count+1]
@@ -861,6 +865,12 @@ struct BatchArgs {
   const int32_t *dirty_list;  // the global bunches found at plan time to hold a dirty tile
   int32_t *stale;             // set when stage 1 finds a dirty tile in an unlisted bunch
   const int4 *bunch_info;     // per global bunch: <matrix, first row, bunch within the matrix, listed>
+  // stage 1's XCD windows: the workgroups b with b mod n_windows = k take the
+  // global bunches window[k] .. window[k+1]-1, in order.  n_windows is kXcds
+  // (one contiguous window per XCD, holding an equal share of the nonzeros)
+  // or 1 for grids of at most kXcds workgroups.
+  int32_t n_windows;
+  int64_t window[kXcds + 1];
 };
 
 // A global bunch's plan entry and its matrix's context, read once per
@@ -878,9 +888,15 @@ __device__ __forceinline__ void batch_entry(const BatchArgs &b, int64_t g, int4 
   }
 }
 
-// gfx950 (one partition) hands consecutive workgroups to its 8 XCDs in turn,
-// workgroup b to XCD b mod 8, and every XCD has its own L2.
-constexpr int kXcds = 8;
+
+// The global bunch of wavefront `wid` of this workgroup in a launch of one
+// wavefront per bunch over the XCD windows, or -1 past its window's end.
+__device__ __forceinline__ int64_t window_bunch(const BatchArgs &b, int wid) {
+  const int G = b.n_windows;
+  const int k = (int)(blockIdx.x % G);
+  const int64_t g = b.window[k] + (int64_t)(blockIdx.x / G) * (blockDim.x / kWave) + wid;
+  return g < b.window[k + 1] ? g : -1;
+}
 
 template <int DT, int W>
 __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
@@ -888,19 +904,17 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   uint32_t *lds_wave = lds_words + wid * stage1_lds_words(W, b.S_max);
-  // One wavefront per thread-bunch, XCD-aware: the grid is a multiple of G
-  // workgroups (or fewer than G), and workgroup blockIdx.x, which runs on XCD
-  // blockIdx.x mod G, takes the (blockIdx.x / G)-th workgroup's worth of
-  // bunches of that XCD's contiguous G-th of the global bunch space.  Each
-  // XCD then works through its own run of matrices in order, and its L2
-  // holds the x of the few matrices in its window instead of those of every
-  // matrix in flight on the chip.  (Any placement of workgroups gives the
-  // same result; the placement only decides the speed.)
-  const int G = min((int)gridDim.x, kXcds);
-  const int64_t per = gridDim.x / G;
-  const int64_t wg = (int64_t)(blockIdx.x % G) * per + blockIdx.x / G;
-  const int64_t g = wg * (blockDim.x / kWave) + wid;
-  if (g >= b.total_bunches) return;
+  // One wavefront per thread-bunch, XCD-aware: workgroup blockIdx.x, which
+  // runs on XCD blockIdx.x mod kXcds, takes the (blockIdx.x / kXcds)-th
+  // workgroup's worth of bunches of that XCD's window, a contiguous run of
+  // the global bunch space holding an eighth of the nonzeros (bunches of
+  // matrices with a larger S hold more).  Each XCD then works through its
+  // own run of matrices in order, and its L2 holds the x of the few matrices
+  // in its window instead of those of every matrix in flight on the chip.
+  // (Any placement of workgroups gives the same result; the placement only
+  // decides the speed.)
+  const int64_t g = window_bunch(b, wid);
+  if (g < 0) return;
   int4 bi;
   MatCtx a;
   batch_entry<W>(b, g, bi, a);
@@ -908,21 +922,21 @@ __global__ __launch_bounds__(256) void sss_stage1_batch(BatchArgs b) {
 }
 
 // The same work as a persistent grid (batch_persistent plans): as many
-// workgroups as stay resident, a multiple of G; the workgroups with
-// blockIdx.x mod G = k stride over the k-th contiguous G-th of the global
-// bunch space, one bunch per wavefront per step.
+// workgroups as stay resident, a multiple of kXcds; the workgroups with
+// blockIdx.x mod kXcds = k stride over window k, one bunch per wavefront per
+// step.
 template <int DT, int W>
 __global__ __launch_bounds__(256) void sss_stage1_batch_persistent(BatchArgs b) {
   extern __shared__ uint32_t lds_words[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   uint32_t *lds_wave = lds_words + wid * stage1_lds_words(W, b.S_max);
-  const int G = min((int)gridDim.x, kXcds);
+  const int G = b.n_windows;
   const int k = (int)(blockIdx.x % G);
   const int wpb = blockDim.x / kWave;
   const int64_t stride = (int64_t)((gridDim.x - k + G - 1) / G) * wpb;  // waves of the workgroups b mod G = k
-  const int64_t hi = b.total_bunches * (k + 1) / G;
-  for (int64_t g = b.total_bunches * k / G + (int64_t)(blockIdx.x / G) * wpb + wid; g < hi; g += stride) {
+  const int64_t hi = b.window[k + 1];
+  for (int64_t g = b.window[k] + (int64_t)(blockIdx.x / G) * wpb + wid; g < hi; g += stride) {
     int4 bi;
     MatCtx a;
     batch_entry<W>(b, g, bi, a);
@@ -938,11 +952,8 @@ template <int DT, int W, bool GATHER>
 __global__ __launch_bounds__(256) void sss_floor_batch(BatchArgs b, typename VT<DT>::y_t *__restrict__ out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  const int G = min((int)gridDim.x, kXcds);
-  const int64_t per = gridDim.x / G;
-  const int64_t wg = (int64_t)(blockIdx.x % G) * per + blockIdx.x / G;
-  const int64_t g = wg * (blockDim.x / kWave) + wid;
-  if (g >= b.total_bunches) return;
+  const int64_t g = window_bunch(b, wid);
+  if (g < 0) return;
   int4 bi;
   MatCtx a;
   batch_entry<W>(b, g, bi, a);
@@ -2089,8 +2100,31 @@ int sss_batch_plan_create(int count, const sss_csr_desc *mats, sss_dtype dt, con
     if (e != hipSuccess) return fail(e);
     wgs1 = std::min<int64_t>(wgs1, (int64_t)cus * std::max(per_cu1, 1));
     if (wgs1 > kXcds) wgs1 -= wgs1 % kXcds;
-  } else if (wgs1 > kXcds) {
-    wgs1 = (wgs1 + kXcds - 1) / kXcds * kXcds;
+  }
+  // the XCD windows: one per XCD when the grid has more than kXcds
+  // workgroups, each a contiguous run of global bunches that holds an equal
+  // share of the nonzeros (a bunch holds S W 64 of its matrix's, the last
+  // one of a matrix fewer), so that matrices with a larger S do not load
+  // their XCD more; else a single window
+  ba.n_windows = wgs1 > kXcds ? kXcds : 1;
+  for (int k = 0; k <= kXcds; ++k) ba.window[k] = nb_all;
+  ba.window[0] = 0;
+  if (ba.n_windows == kXcds) {
+    int k = 1;
+    int64_t before = 0;  // nonzeros of the matrices before matrix i
+    for (int i = 0; i < count && k < kXcds; ++i) {
+      const MatCtx &c = ctx[(size_t)i];
+      const int64_t swt = (int64_t)c.S * WT;
+      while (k < kXcds && c.n_bunches > 0 && before + c.nnz >= tot_nnz * k / kXcds) {
+        const int64_t j = std::min<int64_t>(c.n_bunches, (tot_nnz * k / kXcds - before + swt / 2) / swt);
+        ba.window[k] = std::max(ba.window[k - 1], bb[(size_t)i] + j);
+        ++k;
+      }
+      before += c.nnz;
+    }
+    int64_t per = 0;  // workgroups per XCD: enough for its largest window
+    for (int w = 0; w < kXcds; ++w) per = std::max(per, (ba.window[w + 1] - ba.window[w] + B - 1) / B);
+    if (!p->batch_persistent) wgs1 = kXcds * std::max<int64_t>(per, 1);
   }
   if (wgs1 > INT32_MAX) {  // more bunches than a grid holds: beyond any batch that fits in memory
     (void)hipFree(p->aux);
