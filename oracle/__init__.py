@@ -16,6 +16,8 @@ Contents
   the GPU path produces: tile start rows, segment descriptors, dirty tiles,
   speculator and synchronizer.
 * ``mlp`` -- FP64 forward/backward/Adam for the tile-selector network.
+* ``cg`` -- conjugate gradients (Hestenes and Stiefel) on the row-loop
+  product, the checker of the library's CG calls.
 """
 from __future__ import annotations
 
