@@ -613,11 +613,33 @@ def host_stage2_block(torch, sss, plan, copies, A, x, reps: int = 20) -> dict:
             "sampled_rows_within_1e-12": bool(np.all(np.abs(got - ref) <= 1e-12 * scale))}
 
 
+def _cg_torch_ops(torch, plan, rp, col, v, b, iters: int):
+    """The same CG iteration with PyTorch's dot and elementwise kernels for
+    the vector steps and the plan's product: the comparison for the
+    library's own vector kernels."""
+    x = torch.zeros_like(b)
+    Ap = torch.empty_like(b)
+    r = b.clone()
+    p = r.clone()
+    rr = torch.dot(r, r)
+    for _ in range(iters):
+        plan.execute(rp, col, v, p, Ap)
+        alpha = rr / torch.dot(p, Ap)
+        x.add_(p * alpha)
+        r.sub_(Ap * alpha)
+        rr_new = torch.dot(r, r)
+        p.mul_(rr_new / rr).add_(r)
+        rr = rr_new
+    return x
+
+
 def cg_block(torch, sss, iters: int = 300) -> dict:
     """Iterative-solver use: CG on the 5-point Laplacian of a 1024 x 1024
     grid, one bound plan with the selector's (W, S) reused for every
     product; the plan's one-off analysis time (features, the network, the
-    first-row search), the time per iteration and the product's share."""
+    first-row search), the time per iteration (the library's loop, and one
+    iteration replayed from a graph), the product's share, and the same
+    iteration with PyTorch's vector kernels."""
     import csrgen
     from paper_1504_06474_amd.cg import cg
     A = csrgen.laplacian2d_csr(1024)
@@ -638,6 +660,19 @@ def cg_block(torch, sss, iters: int = 300) -> dict:
     e1.record()
     torch.cuda.synchronize()
     it_us = e0.elapsed_time(e1) / it * 1e3
+    # one library iteration replayed from a graph (the state keeps iterating)
+    cx, cr, cp, cq = (torch.zeros_like(b) for _ in range(4))
+    work = torch.empty(sss.cg_workspace_size() // 8, dtype=torch.float64, device="cuda")
+    sss.cg_start(plan, rp, col, v, b, cx, cr, cp, cq, work)
+    it_graph_us = graph_time_us(torch, lambda c: sss.cg_iterate(plan, rp, col, v, cx, cr, cp, cq, work, 1), [None])
+    _cg_torch_ops(torch, plan, rp, col, v, b, 10)  # warm
+    torch.cuda.synchronize()
+    e0.record()
+    _cg_torch_ops(torch, plan, rp, col, v, b, iters)
+    e1.record()
+    torch.cuda.synchronize()
+    torch_it_us = e0.elapsed_time(e1) / iters * 1e3
+    del cx, cr, cp, cq, work
     y = torch.empty_like(b)
     spmv_us = graph_time_us(torch, lambda c: plan.execute(*c), [(rp, col, v, x_true, y)])
     s1_us = graph_time_us(torch, lambda c: plan.stage1(*c), [(rp, col, v, x_true, y)])
@@ -662,7 +697,10 @@ def cg_block(torch, sss, iters: int = 300) -> dict:
     byts = alg_bytes(A.m, A.n, A.nnz, 8, 8)
     out = {"workload": "laplacian2d_1024", "m": A.m, "nnz": A.nnz, "W": info["W"], "S": info["S"],
            "plan_ms": round(t_plan_ms, 3),
-           "iterations": it, "us_per_iteration": round(it_us, 2), "spmv_us": round(spmv_us, 2),
+           "iterations": it, "us_per_iteration": round(it_us, 2),
+           "us_per_iteration_graph": round(it_graph_us, 2),
+           "us_per_iteration_torch_vector_ops": round(torch_it_us, 2),
+           "vector_kernels_us": round(it_graph_us - spmv_us, 2), "spmv_us": round(spmv_us, 2),
            "spmv_alg_GBps": round(byts / (spmv_us * 1e-6) / 1e9, 1), "stage1_us": round(s1_us, 2),
            "stream_gather_floor_us": round(fl_us, 2),
            "probe_with_rows_best": best_probe, "probe_with_rows_us": round(probe_us[best_probe], 2),

@@ -292,6 +292,10 @@ int sss_plan_destroy(sss_plan p);
 /* The plan's chosen parameters and sizes (host integers, any may be NULL). */
 int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t *n_bunches);
 
+/* The sizes and value type a single-matrix plan was made for (host values,
+ * any pointer may be NULL).  SSS_ERR_INVALID_VALUE for NULL or a batch plan. */
+int sss_plan_shape(sss_plan p, int64_t *m, int64_t *n, int64_t *nnz, sss_dtype *dt);
+
 /* Debug: check row_ptr[0] = 0, monotone row_ptr, row_ptr[m] = nnz and every
  * column in [0, n), on the device.  Synchronises `stream`.  Returns SSS_OK or
  * SSS_ERR_INVALID_CSR. */
@@ -369,6 +373,41 @@ int sss_csr_spmv_autotune(int64_t m, int64_t n, int64_t nnz, const int32_t *row_
 int sss_csr_rowwise(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, const void *val,
                     const void *x, void *y, sss_dtype dt, int lanes_per_row, void *stream);
 const char *sss_rowwise_last_hip_error(void);
+
+/* Conjugate gradients for a symmetric positive definite A, the iterative use
+ * the paper names as the reason to keep CSR (Section 1: a matrix multiplied a
+ * few hundred times, where a format conversion would cost as much as the
+ * solve).  The iteration is Hestenes and Stiefel's: with q = A p,
+ * alpha = (r.r) / (p.q), x += alpha p, r -= alpha q, beta = (r.r)_new / (r.r),
+ * p = r + beta p.  Every product goes through the FP64 plan p
+ * (sss_csr_spmv_execute, so its checks and errors apply); every vector step
+ * and dot product runs in this library's kernels; the step scalars stay on
+ * the device, so the calls only enqueue work on `stream` (no host
+ * synchronisation, no allocation).  Dot products are plain double sums,
+ * per workgroup in a fixed order and then over the workgroups in a fixed
+ * order, so a run repeats bit for bit.  A zero p.q or r.r gives alpha or beta
+ * = 0 instead of a division by zero (b = 0 leaves x where it is).
+ *
+ * Arrays: x, r, dir (the search direction p), q are caller-owned DEVICE
+ * double arrays of m entries (the plan's m; the plan must be square, n = m),
+ * b likewise (read only); work is caller-owned DEVICE memory of
+ * sss_cg_workspace_size bytes, 8-byte aligned, whose first three doubles hold
+ * after every call: [0] r.r of the current residual, [1] r.r before the last
+ * step, [2] b.b (set by sss_cg_start).  A host reads [0] and [2] for the
+ * relative residual sqrt(r.r / b.b).  Calls that share work, or any of the
+ * vectors, must be ordered on one stream.
+ * SSS_ERR_INVALID_VALUE for a NULL or misaligned argument, a batch plan, a
+ * non-square plan or iterations < 0; SSS_ERR_UNSUPPORTED for a plan that is
+ * not SSS_F64. */
+int sss_cg_workspace_size(size_t *bytes);
+/* The start: q = A x, r = b - q, dir = r, work = (r.r, r.r, b.b). */
+int sss_cg_start(sss_plan p, const int32_t *row_ptr, const int32_t *col, const double *val, const double *b,
+                 const double *x, double *r, double *dir, double *q, void *work, void *stream);
+/* `iterations` steps of the iteration from the state that sss_cg_start or the
+ * previous sss_cg_iterate left in x, r, dir and work (q is scratch). */
+int sss_cg_iterate(sss_plan p, const int32_t *row_ptr, const int32_t *col, const double *val, double *x,
+                   double *r, double *dir, double *q, void *work, int iterations, void *stream);
+const char *sss_cg_last_hip_error(void);
 
 /* Measurement aid, not part of the method: the memory floor of stage 1's
  * access pattern under plan p's tiling (W, S, B).  Streams col and val once,

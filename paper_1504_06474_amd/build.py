@@ -6,7 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sss_spmv.hip", "sss_selector.hip", "sss_rowwise.hip", "sss_probe.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sss_spmv.hip", "sss_selector.hip", "sss_rowwise.hip", "sss_probe.hip",
+                                                          "sss_cg.hip")]
 LIB = os.path.join(HERE, "libsss.so")
 
 HIPCC_FLAGS = [

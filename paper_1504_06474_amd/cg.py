@@ -5,11 +5,13 @@ solver: the matrix arrives in CSR, is multiplied a few hundred times, and a
 format conversion would cost about as much as the solve.  Here the plan's
 analysis (sizes, parameters, the bound first row of every thread-bunch) is
 done once, and each iteration is one speculative-segmented-sum product plus
-vector updates on the device (PyTorch elementwise and dot kernels).  The step
-scalars stay on the device, so an iteration does not wait for the host;
-convergence is read every `check_every` iterations.
+the library's own vector and dot-product kernels (sss_cg_start,
+sss_cg_iterate).  The step scalars stay on the device, so an iteration does
+not wait for the host; the residual is read every `check_every` iterations.
 """
 from __future__ import annotations
+
+import math
 
 import torch
 
@@ -19,25 +21,21 @@ from . import sss
 def cg(plan: "sss.Plan", row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, b: torch.Tensor,
        x0: torch.Tensor | None = None, rtol: float = 1e-8, max_iter: int = 1000, check_every: int = 10):
     """Solve A x = b for symmetric positive definite A (CSR, FP64 plan).
-    Returns (x, iterations, [(iteration, ||r|| / ||b||), ...])."""
+    Returns (x, iterations, [(iteration, ||r|| / ||b||), ...]); for b = 0 the
+    history holds ||r|| itself."""
+    if check_every < 1:
+        raise ValueError("check_every must be at least 1")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    Ap = torch.empty_like(b)
-    plan.execute(row_ptr, col, val, x, Ap)
-    r = b - Ap
-    p = r.clone()
-    rr = torch.dot(r, r)
-    b_norm = float(torch.linalg.vector_norm(b))
-    hist = [(0, float(torch.sqrt(rr)) / b_norm)]
+    r, p, q = torch.empty_like(b), torch.empty_like(b), torch.empty_like(b)
+    work = torch.empty(sss.cg_workspace_size() // 8, dtype=torch.float64, device=b.device)
+    sss.cg_start(plan, row_ptr, col, val, b, x, r, p, q, work)
+    rr, bb = work[:3].tolist()[0::2]
+    b_norm = math.sqrt(bb) if bb > 0 else 1.0
+    hist = [(0, math.sqrt(rr) / b_norm)]
     it = 0
     while it < max_iter and hist[-1][1] > rtol:
-        plan.execute(row_ptr, col, val, p, Ap)
-        alpha = rr / torch.dot(p, Ap)
-        x.add_(p * alpha)
-        r.sub_(Ap * alpha)
-        rr_new = torch.dot(r, r)
-        p.mul_(rr_new / rr).add_(r)
-        rr = rr_new
-        it += 1
-        if it % check_every == 0 or it == max_iter:
-            hist.append((it, float(torch.sqrt(rr)) / b_norm))
+        k = min(check_every, max_iter - it)
+        sss.cg_iterate(plan, row_ptr, col, val, x, r, p, q, work, k)
+        it += k
+        hist.append((it, math.sqrt(float(work[0])) / b_norm))
     return x, it, hist

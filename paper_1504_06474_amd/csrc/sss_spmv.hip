@@ -2210,6 +2210,15 @@ int sss_plan_info(sss_plan p, int *W, int *S, int *B, int64_t *n_tiles, int64_t 
   return SSS_OK;
 }
 
+int sss_plan_shape(sss_plan p, int64_t *m, int64_t *n, int64_t *nnz, sss_dtype *dt) {
+  if (!p || p->batch) return SSS_ERR_INVALID_VALUE;
+  if (m) *m = p->m;
+  if (n) *n = p->n;
+  if (nnz) *nnz = p->nnz;
+  if (dt) *dt = static_cast<sss_dtype>(p->dt);
+  return SSS_OK;
+}
+
 int sss_validate_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col, void *stream) {
   if (m < 0 || n < 0 || nnz < 0) return SSS_ERR_INVALID_VALUE;
   if (!row_ptr || (nnz > 0 && !col)) return SSS_ERR_INVALID_VALUE;

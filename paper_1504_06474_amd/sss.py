@@ -106,6 +106,12 @@ def lib():
         L.sss_batch_graph_launch.argtypes = [P, P]
         L.sss_plan_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                     ctypes.POINTER(I64), ctypes.POINTER(I64)]
+        L.sss_plan_shape.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                     ctypes.POINTER(I)]
+        L.sss_cg_workspace_size.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+        L.sss_cg_start.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        L.sss_cg_iterate.argtypes = [P, P, P, P, P, P, P, P, P, I, P]
+        L.sss_cg_last_hip_error.restype = ctypes.c_char_p
         L.sss_validate_csr.argtypes = [I64, I64, I64, P, P, P]
         L.sss_plan_debug_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.sss_plan_debug_dump.argtypes = [P, P, ctypes.c_size_t]
@@ -122,7 +128,8 @@ def lib():
                   "sss_plan_dirty_list", "sss_batch_plan_create", "sss_batch_execute", "sss_batch_graph_launch", "sss_batch_floor_probe",
                   "sss_class_params", "sss_csr_features", "sss_csr_spmv_autotune", "sss_csr_spmv_plan_create_grid", "sss_floor_probe", "sss_batch_plan_create_grid", "sss_csr_rowwise", "sss_csr_spmv_stage2_host", "sss_mlp_forward",
                   "sss_mlp_backward", "sss_mlp_adam", "sss_selector_set", "sss_selector_predict",
-                  "sss_selector_loaded", "sss_gather_probe", "sss_gather_probe_rows", "sss_batch_plan_schedule", "sss_selector_scores"):
+                  "sss_selector_loaded", "sss_gather_probe", "sss_gather_probe_rows", "sss_batch_plan_schedule", "sss_selector_scores",
+                  "sss_plan_shape", "sss_cg_workspace_size", "sss_cg_start", "sss_cg_iterate"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -482,6 +489,40 @@ def csr_rowwise(row_ptr, col, val, x, y, n: int, lanes_per_row: int, stream=None
                                  _ptr(x), _ptr(y), _DTYPES[val.dtype], int(lanes_per_row), _stream(stream)),
            "sss_csr_rowwise")
     return y
+
+
+def cg_workspace_size() -> int:
+    """Bytes of the device work array the CG calls need (sss_cg_workspace_size)."""
+    b = ctypes.c_size_t()
+    _check(lib().sss_cg_workspace_size(ctypes.byref(b)), "sss_cg_workspace_size")
+    return b.value
+
+
+def _check_cg(plan: "Plan", row_ptr, col, val, vectors, work):
+    if plan.dt != F64 or plan.m != plan.n:
+        raise ValueError("CG needs a square FP64 plan")
+    for v in vectors:
+        if v.dtype != torch.float64 or v.numel() < plan.m:
+            raise ValueError("CG vectors must be float64 with at least m entries")
+    plan._check_arrays(row_ptr, col, val, vectors[0], vectors[0])
+    if work.numel() * work.element_size() < cg_workspace_size():
+        raise ValueError("work must hold cg_workspace_size() bytes")
+
+
+def cg_start(plan: "Plan", row_ptr, col, val, b, x, r, p, q, work, stream=None):
+    """q = A x, r = b - q, p = r, and (r.r, r.r, b.b) in work's first three
+    doubles, enqueued on the device (sss_cg_start)."""
+    _check_cg(plan, row_ptr, col, val, (b, x, r, p, q), work)
+    _check(lib().sss_cg_start(plan.handle, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(b), _ptr(x), _ptr(r),
+                              _ptr(p), _ptr(q), _ptr(work), _stream(stream)), "sss_cg_start")
+
+
+def cg_iterate(plan: "Plan", row_ptr, col, val, x, r, p, q, work, iterations: int, stream=None):
+    """`iterations` CG steps from the state in x, r, p and work, enqueued on
+    the device (sss_cg_iterate); q is scratch."""
+    _check_cg(plan, row_ptr, col, val, (x, r, p, q), work)
+    _check(lib().sss_cg_iterate(plan.handle, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(r), _ptr(p),
+                                _ptr(q), _ptr(work), int(iterations), _stream(stream)), "sss_cg_iterate")
 
 
 def plan_grid(row_ptr, col, val, x, y, n: int, reps: int = 5, stream=None) -> "Plan":

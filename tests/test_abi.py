@@ -119,6 +119,13 @@ def test_host_side_argument_checks():
                                    fake, -1, fake, None) == -1
     assert L.sss_gather_probe_rows(fake, None, fake, 10, 10, 0, 0, 1, 4, 0, fake, 1 << 20, ctypes.byref(n), None,
                                    fake, 5, None, None) == -1
+    # CG and the plan's shape: NULL plans and outputs are rejected before any device call
+    assert L.sss_plan_shape(None, None, None, None, None) == -1
+    assert L.sss_cg_start(None, *([None] * 9), None) == -1
+    assert L.sss_cg_iterate(None, *([None] * 8), 1, None) == -1
+    size = ctypes.c_size_t()
+    assert L.sss_cg_workspace_size(None) == -1
+    assert L.sss_cg_workspace_size(ctypes.byref(size)) == 0 and size.value % 8 == 0 and size.value >= 24
     assert L.sss_plan_destroy(None) == 0
 
 
