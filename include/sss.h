@@ -394,8 +394,9 @@ const char *sss_rowwise_last_hip_error(void);
  * sss_cg_workspace_size bytes, 8-byte aligned, whose first three doubles hold
  * after every call: [0] r.r of the current residual, [1] r.r before the last
  * step, [2] b.b (set by sss_cg_start).  A host reads [0] and [2] for the
- * relative residual sqrt(r.r / b.b).  Calls that share work, or any of the
- * vectors, must be ordered on one stream.
+ * relative residual sqrt(r.r / b.b).  The five vectors and work must not
+ * overlap.  Calls that share work, or any of the vectors, must be ordered on
+ * one stream.
  * SSS_ERR_INVALID_VALUE for a NULL or misaligned argument, a batch plan, a
  * non-square plan or iterations < 0; SSS_ERR_UNSUPPORTED for a plan that is
  * not SSS_F64. */
