@@ -1,8 +1,9 @@
 """CG through the library (sss_cg_start, sss_cg_iterate), one bound plan
 reused for every product: the state after k steps against the CG oracle
 (oracle/cg.py) on a 2D Laplacian, a Laplacian larger than one pass of the
-vector kernels' grid with a ragged tail, and an irregular SPD matrix with
-power-law rows; the solution against a dense direct solve; a run repeated
+vector kernels' grid with a ragged tail, an irregular SPD matrix with
+power-law rows, and the benchmark's 1M-row Laplacian in the selector's plan;
+the solution against a dense direct solve; a run repeated
 bit for bit; a zero right-hand side; and the calls' argument checks."""
 import ctypes
 
@@ -53,12 +54,13 @@ def irregular_spd(m, seed):
     return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
 
 
-def matrices():
-    L30 = csrgen.laplacian2d_csr(30)
-    L600 = csrgen.laplacian2d_csr(600)  # 360,000 rows: 1,024 workgroups of the vector kernels stride more than once
-    return {"laplacian_30": (L30.row_ptr, L30.col, L30.val),
-            "laplacian_600": (L600.row_ptr, L600.col, L600.val),
-            "irregular_spd_40k": irregular_spd(40_013, 11)}
+def matrix(name):
+    if name == "irregular_spd_40k":
+        return irregular_spd(40_013, 11)
+    # 600^2 = 360,000 rows: the vector kernels' workgroups take more than one
+    # grid stride, with a ragged tail; 1024^2 is the benchmark's solver workload
+    L = csrgen.laplacian2d_csr(int(name.split("_")[1]))
+    return L.row_ptr, L.col, L.val
 
 
 class State:
@@ -89,16 +91,18 @@ def rel(a, b):
     return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
 
 
-@pytest.mark.parametrize("name", ["laplacian_30", "laplacian_600", "irregular_spd_40k"])
+@pytest.mark.parametrize("name", ["laplacian_30", "laplacian_600", "irregular_spd_40k", "laplacian_1024"])
 def test_cg_steps_match_the_oracle(torch_cuda, name):
     torch = torch_cuda
     from paper_1504_06474_amd import sss
-    rp, col, val = matrices()[name]
+    rp, col, val = matrix(name)
     m = rp.size - 1
     rng = np.random.default_rng(21)
     b = rng.uniform(-1, 1, m)
-    x0 = rng.uniform(-1, 1, m) if name != "laplacian_600" else np.zeros(m)
-    st = State(torch, sss, rp, col, val, b, x0)
+    x0 = rng.uniform(-1, 1, m) if name in ("laplacian_30", "irregular_spd_40k") else np.zeros(m)
+    # the benchmark's launch configuration for its solver workload: the selector's plan
+    kw = {"mode": sss.MODE_SELECTOR} if name == "laplacian_1024" else {}
+    st = State(torch, sss, rp, col, val, b, x0, **kw)
     done = 0
     for k in (0, 1, 2, 5, 20):
         st.iterate(k - done)
