@@ -4,7 +4,6 @@ kernels and parameters, so bitwise the same y, within the double-precision
 tolerance of the oracle and exact on integer-valued inputs.  Two calls in a
 row, the second on a smaller matrix (the static scratch keeps the first
 call's contents)."""
-import ctypes
 
 import numpy as np
 import pytest
