@@ -116,6 +116,48 @@ def test_cg_steps_match_the_oracle(torch_cuda, name):
         assert max(errs.values()) <= REL_TOL, (k, errs)
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 257, 1025, 262_145])
+def test_cg_edge_sizes(torch_cuda, m):
+    """Sizes where the vector kernels have one workgroup, a partial
+    workgroup, or a grid stride one element past a whole number of strides
+    (262,145 = 256 threads x 4 elements x 256 workgroups + 1).  The small
+    systems are solved within the three steps, so r and p are compared
+    against the size of the starting residual and x against the solution."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    rp, col, val = irregular_spd(m, 100 + m)
+    rng = np.random.default_rng(m)
+    b = rng.uniform(-1, 1, m)
+    x0 = rng.uniform(-1, 1, m)
+    st = State(torch, sss, rp, col, val, b, x0)
+    st.iterate(3)
+    got = st.host()
+    want = ocg.cg_steps(rp, col, val, b, x0, 3)
+    rr0 = ocg.cg_steps(rp, col, val, b, x0, 0)["rr"]
+    errs = {"x": rel(got["x"], want["x"])}
+    errs.update({key: np.linalg.norm(got[key] - want[key]) / np.sqrt(rr0) for key in ("r", "p")})
+    errs.update({key: abs(got[key] - want[key]) / rr0 for key in ("rr", "rr_prev")})
+    errs["bb"] = abs(got["bb"] - want["bb"]) / want["bb"]
+    note(f"  m={m}: " + " ".join(f"{key} {e:.1e}" for key, e in errs.items()))
+    assert all(np.isfinite(list(errs.values())))
+    assert max(errs.values()) <= REL_TOL, errs
+
+
+def test_cg_empty_system(torch_cuda):
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    plan = sss.Plan(0, 0, 0)
+    rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    col = torch.zeros(0, dtype=torch.int32, device="cuda")
+    val = torch.zeros(0, dtype=torch.float64, device="cuda")
+    vec = [torch.zeros(0, dtype=torch.float64, device="cuda") for _ in range(5)]
+    work = torch.full((sss.cg_workspace_size() // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    sss.cg_start(plan, rp, col, val, *vec, work)
+    sss.cg_iterate(plan, rp, col, val, *vec[1:], work, 3)
+    torch.cuda.synchronize()
+    assert work[:3].tolist() == [0.0, 0.0, 0.0]
+
+
 def test_cg_solution_matches_direct_solve(torch_cuda):
     torch = torch_cuda
     from paper_1504_06474_amd import sss
