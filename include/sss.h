@@ -386,7 +386,7 @@ const char *sss_rowwise_last_hip_error(void);
  * synchronisation, no allocation).  Dot products are plain double sums,
  * per workgroup in a fixed order and then over the workgroups in a fixed
  * order, so a run repeats bit for bit.  A zero p.q or r.r gives alpha or beta
- * = 0 instead of a division by zero (b = 0 leaves x where it is).
+ * = 0 instead of a division by zero (b = 0 from x = 0 stays at 0).
  *
  * Arrays: x, r, dir (the search direction p), q are caller-owned DEVICE
  * double arrays of m entries (the plan's m; the plan must be square, n = m),
