@@ -63,3 +63,14 @@ def test_bench_json_has_no_non_finite_numbers():
     line = json.dumps(bench._finite({"a": float("nan"), "b": [1.5, float("-inf")], "c": {"d": float("inf")}}),
                       allow_nan=False)
     assert json.loads(line) == {"a": None, "b": [1.5, None], "c": {"d": None}}
+
+
+def test_algorithmic_bytes_of_the_benchmark_matrix():
+    """The roofline's bytes per product: each of the 19,189,716 entries once
+    (8-byte value, 4-byte column), row_ptr's 1,000,001 int32 offsets, x and
+    y once each (1,000,000 doubles each); the FP32 form halves values and
+    vectors."""
+    assert bench.alg_bytes(1_000_000, 1_000_000, 19_189_716, 8, 8) == 250_276_596
+    assert bench.alg_bytes(1_000_000, 1_000_000, 19_189_716, 4, 4) == 19_189_716 * 8 + 4_000_004 + 8_000_000
+    # rectangular: x has n entries, y has m
+    assert bench.alg_bytes(3, 5, 7, 8, 8) == 7 * 12 + 4 * 4 + 5 * 8 + 3 * 8
