@@ -72,3 +72,26 @@ def test_general_values_f64(torch_cuda, lanes):
     A, x = csrgen.config1()
     assert_f64_parity(run(torch_cuda, A, x, lanes), oracle.spmv(A.row_ptr, A.col, A.val, x),
                       oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
+
+
+@pytest.mark.parametrize("lanes", [1, 64])
+def test_benchmark_matrix_every_row(torch_cuda, lanes):
+    """The 1M-row power-law matrix (19.2M nonzeros, a 197,189-entry row), as
+    the benchmark times the comparators: every row against the oracle within
+    the bound of plain summation in any order, gamma_k (|A||x|)_i with
+    gamma_k = k u / (1 - k u), k the row's length and u = 2^-53, plus the
+    oracle's own error (compensated: u |y_i| + gamma_k^2 (|A||x|)_i)."""
+    A, x = csrgen.config2()
+    got = run(torch_cuda, A, x, lanes)
+    want = oracle.spmv(A.row_ptr, A.col, A.val, x)
+    scale = oracle.abs_spmv(A.row_ptr, A.col, A.val, x)
+    k = np.diff(A.row_ptr).astype(np.float64)
+    u = 2.0 ** -53
+    gamma = k * u / (1.0 - k * u)
+    bound = gamma * scale + u * np.abs(want) + gamma * gamma * scale
+    err = np.abs(got - want)
+    ratio = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0), 0.0)
+    i = int(np.argmax(ratio))
+    note(f"  lanes={lanes}: max err / bound {ratio[i]:.3f} (row length {int(k[i])})")
+    assert np.all(err <= bound), int(np.sum(err > bound))
+    assert np.all(got[k == 0] == 0.0)
