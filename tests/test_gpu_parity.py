@@ -590,3 +590,27 @@ def test_stage2_on_host(torch_cuda, name, WS):
     yh = y.cpu().numpy().copy()
     plan.stage2_host(A.row_ptr, yh)
     assert_exact(yh, oracle.spmv(A.row_ptr, A.col, A.val, x))
+
+
+def test_stage2_on_host_benchmark_matrix(torch_cuda):
+    """The paper's split at full size, as the benchmark times it: the 1M-row
+    power-law matrix with the rows bound at plan time (stage 1 on the device,
+    stage 2 on a host core); every row within 1e-12 (|A||x|)_i of the oracle.
+    The host adds a row's carries in bunch order and the device adds runs of
+    more than 16 bunches by a tree, so the two agree bit for bit except on
+    the rows that such runs end in."""
+    torch = torch_cuda
+    from paper_1504_06474_amd import sss
+    A, x = csrgen.config2()
+    rp, col, v, xx = to_dev(A, x)
+    plan = sss.Plan(A.m, A.n, A.nnz, bind_rows=True, row_ptr=rp)
+    y_dev = plan.execute(rp, col, v, xx)
+    y = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+    plan.stage1(rp, col, v, xx, y)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy().copy()
+    plan.stage2_host(A.row_ptr, yh)
+    assert_f64_parity(yh, oracle.spmv(A.row_ptr, A.col, A.val, x), oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
+    # rows shorter than 16 bunches' worth of nonzeros get no tree-summed run
+    short = np.diff(A.row_ptr) < 16 * plan.info()["W"] * 64 * plan.info()["S"]
+    assert np.array_equal(yh[short], y_dev.cpu().numpy()[short])
