@@ -74,14 +74,16 @@ def test_general_values_f64(torch_cuda, lanes):
                       oracle.abs_spmv(A.row_ptr, A.col, A.val, x))
 
 
+@pytest.mark.parametrize("matrix", ["powerlaw_1M", "zipf18_4M"])
 @pytest.mark.parametrize("lanes", [1, 64])
-def test_benchmark_matrix_every_row(torch_cuda, lanes):
-    """The 1M-row power-law matrix (19.2M nonzeros, a 197,189-entry row), as
-    the benchmark times the comparators: every row against the oracle within
+def test_benchmark_matrix_every_row(torch_cuda, lanes, matrix):
+    """The 1M-row power-law matrix (19.2M nonzeros, a 197,189-entry row) and
+    the 4M-row Zipf 1.8 matrix (80.3M nonzeros), on which the benchmark times
+    the comparators: every row against the oracle within
     the bound of plain summation in any order, gamma_k (|A||x|)_i with
     gamma_k = k u / (1 - k u), k the row's length and u = 2^-53, plus the
     oracle's own error (compensated: u |y_i| + gamma_k^2 (|A||x|)_i)."""
-    A, x = csrgen.config2()
+    A, x = csrgen.config2() if matrix == "powerlaw_1M" else csrgen.config5()
     got = run(torch_cuda, A, x, lanes)
     want = oracle.spmv(A.row_ptr, A.col, A.val, x)
     scale = oracle.abs_spmv(A.row_ptr, A.col, A.val, x)
